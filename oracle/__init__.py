@@ -1,0 +1,118 @@
+"""CPU oracle for the upper hood -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  The GPU library never loads it and shares no
+code with it; the two meet only through the seeded generators in ``synth``.
+
+Contents:
+  * ``hull_oracle.c`` (built into ``_build/liboracle_hull.so``): the exact
+    integer Andrew monotone chain (upper half) -- the plain definition of the
+    upper hood the method computes;
+  * ``brute``      -- O(n^3) evaluation of the hood's definition (tiny n);
+  * ``invariants`` -- exact checks that characterise the strict upper hood;
+  * ``bridge``     -- the per-merge quantities of the paper's match-and-merge
+    step (tangent classifiers g and f, the common tangent) by brute force.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hull_oracle.c")
+_BUILD = os.path.join(_HERE, "_build")
+_LIB_PATH = os.path.join(_BUILD, "liboracle_hull.so")
+
+# status codes (the oracle's own copy of the documented contract values)
+OK = 0
+ERR_ARG = -1
+ERR_UNSORTED = -10
+ERR_RANGE = -11
+ERR_GRID = -12
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/_build/liboracle_hull.so."""
+    os.makedirs(_BUILD, exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH) or (
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC",
+                               "-Wall", "-Werror", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or (
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        i64, p = ctypes.c_int64, ctypes.c_void_p
+        lib.oracle_upper_hull.argtypes = [p, i64, p, p]
+        lib.oracle_upper_hull.restype = ctypes.c_int
+        lib.oracle_upper_hull_batched.argtypes = [p, p, i64, p, p]
+        lib.oracle_upper_hull_batched.restype = ctypes.c_int
+        lib.oracle_orient_signs.argtypes = [p, p, p, i64, p]
+        lib.oracle_orient_signs.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _pts(xy) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(xy, dtype=np.float32).reshape(-1, 2))
+    return a
+
+
+def upper_hull_status(xy):
+    """(status, indices).  status 0 on success, else a negative error code."""
+    a = _pts(xy)
+    n = a.shape[0]
+    out = np.empty(max(n, 1), dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    rc = _load().oracle_upper_hull(a.ctypes.data, n, out.ctypes.data,
+                                   ctypes.addressof(cnt))
+    return rc, out[: cnt.value].copy()
+
+
+def upper_hull(xy) -> np.ndarray:
+    """Indices of the strict upper-hood corners, left to right (int32)."""
+    rc, idx = upper_hull_status(xy)
+    if rc != OK:
+        raise ValueError(f"oracle: invalid input (status {rc})")
+    return idx
+
+
+def upper_hull_batched(xy, offsets):
+    """Per-set hulls.  Returns (out_idx, counts): set s's corner indices,
+    relative to offsets[s], are out_idx[offsets[s] : offsets[s] + counts[s]]."""
+    a = _pts(xy)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    S = off.shape[0] - 1
+    out = np.zeros(max(a.shape[0], 1), dtype=np.int32)
+    counts = np.zeros(max(S, 1), dtype=np.int64)
+    rc = _load().oracle_upper_hull_batched(a.ctypes.data, off.ctypes.data, S,
+                                           out.ctypes.data, counts.ctypes.data)
+    if rc != OK:
+        raise ValueError(f"oracle: invalid input (status {rc})")
+    return out, counts[:S]
+
+
+def orient_signs(a, b, c) -> np.ndarray:
+    """Exact sign of det(b - a, c - a) for each row (int8 in {-1, 0, 1})."""
+    a, b, c = _pts(a), _pts(b), _pts(c)
+    m = a.shape[0]
+    assert b.shape[0] == m and c.shape[0] == m
+    out = np.empty(max(m, 1), dtype=np.int8)
+    rc = _load().oracle_orient_signs(a.ctypes.data, b.ctypes.data,
+                                     c.ctypes.data, m, out.ctypes.data)
+    if rc != OK:
+        raise ValueError(f"oracle: invalid coordinate (status {rc})")
+    return out[:m].copy()

@@ -1,0 +1,179 @@
+/*
+ * Upper-hood oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, obviously correct CPU computation of what the GPU path
+ * computes: the upper hood (upper convex hull, closed by downward vertical
+ * rays) of a set of points given in left-to-right order, returned as the
+ * input indices of its corners, left to right.  Only the tests, the smoke
+ * check and the benchmark's CPU baseline may load this library; the product
+ * path never calls it.  It shares no code, header or constant generator with
+ * the GPU library.
+ *
+ * Paper: C. O Dunlaing, "CUDA implementation of Wagener's 2D convex hull PRAM
+ * algorithm".  What is followed here:
+ *   - problem statement (section "Wagener's algorithm, CUDA version"): the
+ *     input is n points in left-to-right order with x in [0, 1]; the output
+ *     is the upper hood of the set;
+ *   - orientation convention (the left_of predicate described just before
+ *     the g and f classifiers): r is left of the directed segment pq iff
+ *     det(q - p, r - p) > 0; with p.x < q.x "left" means "above";
+ *   - vertical closure: the classifiers g and f treat a missing neighbour
+ *     as a point directly below the end corner, i.e. the hood is closed by
+ *     downward vertical rays, so at any x only the highest point can be a
+ *     corner.
+ *
+ * Readings where the paper is silent (it assumes no three points collinear,
+ * n a power of two, and no floating-point error):
+ *   - strict hood: a point in the relative interior of a hood edge is not a
+ *     corner (pop while orient >= 0);
+ *   - equal x: only the highest point of a run of equal x can be a corner;
+ *     identical points resolve to the lowest index;
+ *   - exactness: coordinates are read as exact integers on the 2^-30 grid
+ *     (every float32 in [2^-7, 1] is on it), orientation is evaluated in
+ *     128-bit integers, so every sign is exact;
+ *   - any n >= 0 is accepted.
+ *
+ * Algorithm (Andrew's monotone chain, upper half), steps in order:
+ *   1. convert each coordinate to an exact integer, validating the contract;
+ *   2. keep one representative per run of equal x (max y, lowest index);
+ *   3. scan representatives left to right, popping the stack top while the
+ *      new point is on or above the line through the top two, then push.
+ *
+ * The chain's correctness is not taken on trust: the tests pin it against an
+ * O(n^3) brute-force evaluation of the hood's definition, against Qhull on
+ * points in general position, and against closed forms and invariants.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef __int128 i128;
+
+/* status codes (values mirror the library's documented contract) */
+#define OR_OK 0
+#define OR_ERR_ARG (-1)
+#define OR_ERR_UNSORTED (-10)
+#define OR_ERR_RANGE (-11)
+#define OR_ERR_GRID (-12)
+
+#define GRID_SCALE 1073741824.0 /* 2^30 */
+
+/* Step 1: exact integer coordinate on the 2^-30 grid.  Returns 0 or an
+ * error code.  x must lie in [0, 1], y in [-1, 1]; NaN fails the range test. */
+static int grid_int(float v, double lo, double hi, int64_t *out) {
+  double d = (double)v;
+  if (!(d >= lo && d <= hi)) return OR_ERR_RANGE;
+  double s = d * GRID_SCALE; /* exact: power-of-two scaling of a float */
+  double t = floor(s);
+  if (t != s) return OR_ERR_GRID;
+  *out = (int64_t)t;
+  return OR_OK;
+}
+
+/* det(b - a, c - a): > 0 iff c is left of (above) the directed line a->b. */
+static i128 orient(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t cx,
+                   int64_t cy) {
+  return (i128)(bx - ax) * (i128)(cy - ay) - (i128)(by - ay) * (i128)(cx - ax);
+}
+
+/* Validate and convert all points; returns 0 or an error code. */
+static int convert(const float *xy, int64_t n, int64_t *X, int64_t *Y) {
+  for (int64_t i = 0; i < n; ++i) {
+    int rc = grid_int(xy[2 * i], 0.0, 1.0, &X[i]);
+    if (rc) return rc;
+    rc = grid_int(xy[2 * i + 1], -1.0, 1.0, &Y[i]);
+    if (rc) return rc;
+    if (i > 0 && X[i] < X[i - 1]) return OR_ERR_UNSORTED;
+  }
+  return OR_OK;
+}
+
+/* Steps 2-3 on already converted coordinates.  idx_base is added to the
+ * written indices (0 for a single set).  Returns the corner count. */
+static int64_t chain(const int64_t *X, const int64_t *Y, int64_t n,
+                     int32_t *out_idx) {
+  int64_t h = 0; /* out_idx doubles as the stack */
+  int64_t i = 0;
+  while (i < n) {
+    /* step 2: representative of the run of equal x starting at i */
+    int64_t rep = i, j = i + 1;
+    while (j < n && X[j] == X[i]) {
+      if (Y[j] > Y[rep]) rep = j; /* strict: ties keep the lowest index */
+      ++j;
+    }
+    i = j;
+    /* step 3: pop while the new point is on or above line (h-2, h-1) */
+    while (h >= 2) {
+      int64_t a = out_idx[h - 2], b = out_idx[h - 1];
+      if (orient(X[a], Y[a], X[b], Y[b], X[rep], Y[rep]) >= 0)
+        --h;
+      else
+        break;
+    }
+    out_idx[h++] = (int32_t)rep;
+  }
+  return h;
+}
+
+/* Upper hood of xy[0..n) (x, y interleaved float32).  out_idx needs room for
+ * n entries.  Returns 0 and sets *out_count, or a negative error code. */
+int oracle_upper_hull(const float *xy, int64_t n, int32_t *out_idx,
+                      int64_t *out_count) {
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!xy || !out_idx)) || !out_count)
+    return OR_ERR_ARG;
+  *out_count = 0;
+  if (n == 0) return OR_OK;
+  int64_t *X = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  int64_t *Y = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  if (!X || !Y) {
+    free(X);
+    free(Y);
+    return OR_ERR_ARG;
+  }
+  int rc = convert(xy, n, X, Y);
+  if (rc == OR_OK) *out_count = chain(X, Y, n, out_idx);
+  free(X);
+  free(Y);
+  return rc;
+}
+
+/* Many independent sets: set s is xy[offsets[s] .. offsets[s+1]); its corner
+ * indices (relative to offsets[s]) are written at out_idx + offsets[s] and
+ * its count to out_counts[s].  Returns 0 or the first error code; a set
+ * that fails gets its error code as its count. */
+int oracle_upper_hull_batched(const float *xy, const int64_t *offsets,
+                              int64_t num_sets, int32_t *out_idx,
+                              int64_t *out_counts) {
+  if (num_sets < 0 || !offsets || (num_sets > 0 && !out_counts))
+    return OR_ERR_ARG;
+  int first_err = OR_OK;
+  for (int64_t s = 0; s < num_sets; ++s) {
+    int64_t lo = offsets[s], hi = offsets[s + 1];
+    int64_t cnt = 0;
+    int rc = oracle_upper_hull(xy + 2 * lo, hi - lo, out_idx + lo, &cnt);
+    out_counts[s] = rc ? rc : cnt;
+    if (rc && !first_err) first_err = rc;
+  }
+  return first_err;
+}
+
+/* Exact sign of det(b - a, c - a) for m triples of float points (each array
+ * holds x, y interleaved).  Writes -1, 0 or +1.  Returns 0 or an error code
+ * (off-grid or out-of-range coordinate). */
+int oracle_orient_signs(const float *a, const float *b, const float *c,
+                        int64_t m, int8_t *out_sign) {
+  for (int64_t i = 0; i < m; ++i) {
+    int64_t v[6];
+    const float *src[3] = {a + 2 * i, b + 2 * i, c + 2 * i};
+    for (int k = 0; k < 3; ++k) {
+      int rc = grid_int(src[k][0], 0.0, 1.0, &v[2 * k]);
+      if (rc) return rc;
+      rc = grid_int(src[k][1], -1.0, 1.0, &v[2 * k + 1]);
+      if (rc) return rc;
+    }
+    i128 d = orient(v[0], v[1], v[2], v[3], v[4], v[5]);
+    out_sign[i] = (int8_t)((d > 0) - (d < 0));
+  }
+  return OR_OK;
+}
