@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Upper-hood throughput on one MI355X.
+
+One step = one device-resident upper-hood computation of the whole workload
+(every round of Wagener merges: tile kernel, then merge passes), inputs
+already resident in HBM.  Default workload: one set of n = 2^27 points, x iid
+on the 2^-27 grid (sorted, float32), y uniform -- the bandwidth-roofline
+configuration.  Prints ONE JSON line on stdout (progress goes to stderr).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "input points/sec (upper hull, 1 GPU) + % HBM roofline; batched vs plain"
+KERNEL_SOURCES = ["paper_1203_5004_amd/csrc/wagener_hull.hip",
+                  "paper_1203_5004_amd/csrc/uh_device.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, strip: int):
+    """HBM bytes per tile-kernel launch from the committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != kernel_hash() or d.get("strip") != strip:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+class HipEvents:
+    """Raw hipEvent_t handles for the library's profiling hook."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self):
+        e = ctypes.c_void_p()
+        assert self.hip.hipEventCreate(ctypes.byref(e)) == 0
+        return e.value
+
+    def elapsed_ms(self, a, b) -> float:
+        ms = ctypes.c_float()
+        assert self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a),
+                                            ctypes.c_void_p(b)) == 0
+        return ms.value
+
+    def destroy(self, e):
+        self.hip.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def cpu_baseline(pts_np, off, budget_s: float):
+    import oracle
+    t_total, reps = 0.0, 0
+    out = cnt = None
+    while reps < 1 or (t_total < budget_s and reps < 5):
+        t0 = time.perf_counter()
+        out, cnt = oracle.upper_hull_batched(pts_np, off)
+        t_total += time.perf_counter() - t0
+        reps += 1
+    return len(pts_np) * reps / t_total, reps, t_total, out, cnt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform_2^27")
+    ap.add_argument("--strip", type=int, default=16)
+    ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the path shards by contiguous point ranges, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1203_5004_amd as uh
+    import synth
+
+    if args.workload not in synth.WORKLOADS:
+        sys.exit(f"unknown workload {args.workload}; choose from {list(synth.WORKLOADS)}")
+    t0 = time.perf_counter()
+    pts_np, off = synth.WORKLOADS[args.workload][0]()
+    log(f"[bench] generated {args.workload}: {len(pts_np)} points, {len(off) - 1} sets "
+        f"in {time.perf_counter() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(pts_np).to(dev)
+    N, S = len(pts_np), len(off) - 1
+    flags = uh.UH_FLAG_GRAPH if args.graph else 0
+    plan = uh.upper_hull_plan_create(off, strip=args.strip, flags=flags)
+    out_idx = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
+    out_cnt = torch.empty(S, dtype=torch.int32, device=dev)
+    stats = torch.zeros((S, 2), dtype=torch.int64, device=dev)
+
+    ev = HipEvents()
+    probes = []
+    if not args.graph:
+        probes = [(ev.create(), ev.create()) for _ in range(args.steps)]
+
+    # correctness of what is about to be timed: counters + status
+    plan.run(pts, out_idx, out_cnt, stats)
+    torch.cuda.synchronize()
+    cnt_np = out_cnt.cpu().numpy()
+    if np.any(cnt_np < 0):
+        sys.exit(f"bench: data error status {cnt_np.min()}")
+    st = stats.cpu().numpy()
+    evals, fallbacks = int(st[:, 0].sum()), int(st[:, 1].sum())
+
+    for _ in range(args.warmup):
+        plan.run(pts, out_idx, out_cnt)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps, {plan.launches} launches per step)")
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(args.steps):
+        if probes:
+            plan.set_probe(*probes[k])
+        plan.run(pts, out_idx, out_cnt)
+    end.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    ms_step = total_ms / args.steps
+    value = N / (ms_step * 1e-3)
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} points/s")
+
+    tile_ms = None
+    if probes:
+        plan.set_probe(None, None)
+        tile_ms = sum(ev.elapsed_ms(a, b) for a, b in probes) / len(probes)
+        for a, b in probes:
+            ev.destroy(a)
+            ev.destroy(b)
+
+    h_total = int(cnt_np.sum())
+    alg_tile = 8.0 * N  # every point read once (float2)
+    roofline = None
+    if tile_ms:
+        achieved = alg_tile / (tile_ms * 1e-3) / 1e9
+        traffic = load_traffic(args.workload, args.strip)
+        roofline = {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "tile_kernel_ms": round(tile_ms, 4)}
+    path_gbs = (8.0 * N + 4.0 * h_total) / (ms_step * 1e-3) / 1e9
+
+    cpu = None
+    checked = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle ...")
+        rate, reps, secs, ref_out, ref_cnt = cpu_baseline(pts_np, off, args.cpu_budget)
+        cpu = {"value": round(rate, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
+               "sample": f"whole workload ({N} points, {S} sets), {reps} run(s), "
+                         f"{secs:.1f} s, single thread"}
+        got = out_idx.cpu().numpy()
+        checked = bool(np.array_equal(cnt_np, ref_cnt.astype(np.int32)) and all(
+            np.array_equal(got[off[s]:off[s] + cnt_np[s]], ref_out[off[s]:off[s] + cnt_np[s]])
+            for s in range(S)))
+        log(f"[bench] oracle {rate:.4g} points/s; GPU result equals oracle: {checked}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_points": N, "sets": S, "strip": args.strip,
+                   "tile_points": 256 * args.strip, "launches_per_step": plan.launches,
+                   "graph": bool(args.graph), "corners": h_total,
+                   "orient_evals_per_point": round(evals / max(N, 1), 3),
+                   "fallback_rate": (fallbacks / evals) if evals else 0.0,
+                   "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                   "matches_oracle": checked},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

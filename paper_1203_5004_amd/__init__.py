@@ -1,0 +1,224 @@
+"""Python binding of the MI355X upper-hood library (libwagener_hull.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/wagener_hull.h.  PyTorch
+provides device memory and the current stream.  There is no CPU fallback:
+if the library has not been built, every call raises.
+
+    import torch, paper_1203_5004_amd as uh
+    idx, cnt = uh.upper_hull(points)          # points: cuda float32 [n, 2]
+    plan = uh.upper_hull_plan_create(offsets) # host offsets, len S + 1
+    plan.run(points, out_idx, out_counts, stats)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libwagener_hull.so")
+
+UH_OK = 0
+UH_ERR_ARG = -1
+UH_ERR_ALLOC = -2
+UH_ERR_HIP = -3
+UH_ERR_CAPTURE = -4
+UH_ERR_UNSORTED = -10
+UH_ERR_RANGE = -11
+UH_ERR_GRID = -12
+
+UH_FLAG_FORCE_FALLBACK = 1
+UH_FLAG_NO_VALIDATE = 2
+UH_FLAG_GRAPH = 4
+
+EXPORTS = (
+    "upper_hull_status_string", "upper_hull", "upper_hull_plan_create",
+    "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
+    "upper_hull_plan_set_probe",
+    "upper_hull_bridge", "upper_hull_orient",
+)
+
+
+class upper_hull_stats(ctypes.Structure):
+    _fields_ = [("orient_evals", ctypes.c_uint64), ("fallbacks", ctypes.c_uint64)]
+
+
+class upper_hull_config(ctypes.Structure):
+    _fields_ = [("strip", ctypes.c_int32), ("fan_in", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1203_5004_amd.build` "
+            "(the library has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.upper_hull_status_string.argtypes = [ctypes.c_int]
+    lib.upper_hull_status_string.restype = ctypes.c_char_p
+    lib.upper_hull.argtypes = [p, i64, p, p, p]
+    lib.upper_hull.restype = ctypes.c_int
+    lib.upper_hull_plan_create.argtypes = [p, i32, p, ctypes.POINTER(p)]
+    lib.upper_hull_plan_create.restype = ctypes.c_int
+    lib.upper_hull_plan_run.argtypes = [p, p, p, p, p, p]
+    lib.upper_hull_plan_run.restype = ctypes.c_int
+    lib.upper_hull_plan_destroy.argtypes = [p]
+    lib.upper_hull_plan_destroy.restype = None
+    lib.upper_hull_plan_launches.argtypes = [p]
+    lib.upper_hull_plan_launches.restype = ctypes.c_int
+    lib.upper_hull_plan_set_probe.argtypes = [p, p, p]
+    lib.upper_hull_plan_set_probe.restype = ctypes.c_int
+    lib.upper_hull_bridge.argtypes = [p, i32, p, i32, i32, p, p]
+    lib.upper_hull_bridge.restype = ctypes.c_int
+    lib.upper_hull_orient.argtypes = [p, p, p, i64, p, p, i32, p]
+    lib.upper_hull_orient.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def upper_hull_status_string(status: int) -> str:
+    return load_library().upper_hull_status_string(int(status)).decode()
+
+
+def _check(rc: int):
+    if rc != UH_OK:
+        raise RuntimeError(f"upper_hull: {upper_hull_status_string(rc)} ({rc})")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_tensor(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def upper_hull(points, out_idx=None, out_count=None, stream=None):
+    """Upper-hood corner indices of points (cuda float32 [n, 2], x-sorted).
+
+    Returns (out_idx int32[n], out_count int32[1]) on the device; the first
+    out_count[0] entries of out_idx are the corners, left to right (a
+    negative count is a data-error status).  Asynchronous on `stream`."""
+    torch = _torch()
+    _dev_tensor(points, torch.float32, "points")
+    n = points.shape[0]
+    if points.dim() != 2 or points.shape[1] != 2:
+        raise ValueError("points must have shape [n, 2]")
+    if out_idx is None:
+        out_idx = torch.empty(max(n, 1), dtype=torch.int32, device=points.device)
+    if out_count is None:
+        out_count = torch.empty(1, dtype=torch.int32, device=points.device)
+    _dev_tensor(out_idx, torch.int32, "out_idx")
+    _dev_tensor(out_count, torch.int32, "out_count")
+    _check(load_library().upper_hull(_ptr(points), n, _ptr(out_idx), _ptr(out_count),
+                                     _stream(stream)))
+    return out_idx, out_count
+
+
+class Plan:
+    """A batched plan (schedule + workspace) for fixed set sizes."""
+
+    def __init__(self, set_offsets, strip=0, fan_in=0, flags=0):
+        off = np.ascontiguousarray(np.asarray(set_offsets, dtype=np.int64))
+        if off.ndim != 1 or off.shape[0] < 2:
+            raise ValueError("set_offsets must be 1-D with at least 2 entries")
+        self.set_offsets = off
+        self.num_sets = off.shape[0] - 1
+        self.total = int(off[-1])
+        cfg = upper_hull_config(strip, fan_in, flags)
+        h = ctypes.c_void_p()
+        _check(load_library().upper_hull_plan_create(
+            off.ctypes.data, self.num_sets, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def launches(self) -> int:
+        return load_library().upper_hull_plan_launches(self._h)
+
+    def set_probe(self, before, after):
+        """Record raw hipEvent_t handles (ints) around the tile kernel."""
+        _check(load_library().upper_hull_plan_set_probe(
+            self._h, ctypes.c_void_p(before), ctypes.c_void_p(after)))
+
+    def run(self, points, out_idx, out_counts, stats=None, stream=None):
+        torch = _torch()
+        _dev_tensor(points, torch.float32, "points")
+        _dev_tensor(out_idx, torch.int32, "out_idx")
+        _dev_tensor(out_counts, torch.int32, "out_counts")
+        if points.numel() != 2 * self.total or out_idx.numel() < self.total:
+            raise ValueError("buffer sizes do not match the plan")
+        if out_counts.numel() < self.num_sets:
+            raise ValueError("out_counts too small")
+        if stats is not None:
+            _dev_tensor(stats, torch.int64, "stats")
+            if stats.numel() < 2 * self.num_sets:
+                raise ValueError("stats needs 2 int64 per set")
+        _check(load_library().upper_hull_plan_run(
+            self._h, _ptr(points), _ptr(out_idx), _ptr(out_counts), _ptr(stats),
+            _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load_library().upper_hull_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def upper_hull_plan_create(set_offsets, strip=0, fan_in=0, flags=0) -> Plan:
+    return Plan(set_offsets, strip, fan_in, flags)
+
+
+def upper_hull_bridge(P, Q, lanes=64, stream=None):
+    """Bridge (a, b) of two hoods given as cuda float32 [h, 2] corner lists."""
+    torch = _torch()
+    _dev_tensor(P, torch.float32, "P")
+    _dev_tensor(Q, torch.float32, "Q")
+    out = torch.empty(2, dtype=torch.int32, device=P.device)
+    _check(load_library().upper_hull_bridge(_ptr(P), P.shape[0], _ptr(Q), Q.shape[0],
+                                            lanes, _ptr(out), _stream(stream)))
+    return out
+
+
+def upper_hull_orient(a, b, c, force_fallback=False, stream=None):
+    """Exact orientation signs (int8) and fallback flags (uint8) per row."""
+    torch = _torch()
+    for t, nm in ((a, "a"), (b, "b"), (c, "c")):
+        _dev_tensor(t, torch.float32, nm)
+    m = a.shape[0]
+    sign = torch.empty(max(m, 1), dtype=torch.int8, device=a.device)
+    fb = torch.empty(max(m, 1), dtype=torch.uint8, device=a.device)
+    _check(load_library().upper_hull_orient(_ptr(a), _ptr(b), _ptr(c), m, _ptr(sign),
+                                            _ptr(fb), int(bool(force_fallback)),
+                                            _stream(stream)))
+    return sign[:m], fb[:m]

@@ -1,0 +1,880 @@
+// wagener_hull.hip -- kernels, schedule and C ABI of the upper-hood library.
+//
+// Paper: C. O Dunlaing, "CUDA implementation of Wagener's 2D convex hull PRAM
+// algorithm".  The paper's program copies the padded hood array to the GPU,
+// launches match_and_merge once per stage (d = 2, 4, ..., n/2) and copies it
+// back after every stage.  Here the same rounds of pairwise hood merges run
+// device-resident, in three kinds of launch enqueued back to back:
+//
+//   init_kernel   clears per-set status and counters.
+//   tile_kernel   one workgroup per tile of T = 256 * K points of one set:
+//                 coalesced load (plus contract checks) into LDS; each lane
+//                 builds the hood of its strip of K consecutive points
+//                 serially (the first step of the paper's work-optimal
+//                 variant in its conclusions); then log2(256) = 8 rounds of
+//                 Wagener merges of adjacent strip hoods in LDS, each merge
+//                 finding its bridge with the sampled search of one wave and
+//                 compacting P[0..a] ++ Q[b..]; the tile hood goes to the
+//                 workspace (or straight to the output for a one-tile set).
+//   merge_kernel  one workgroup merges up to F consecutive hoods of the
+//                 previous level of one set through log2(F) further rounds,
+//                 in LDS when they fit, else in place in the workspace.
+//                 Repeated until every set has a single hood.
+//
+// Hoods are stored compactly (no REMOTE padding): a block's corners are a
+// prefix of its slot, with a count.  The workspace holds, at each point's
+// position, at most one corner (x, y) and its set-relative index, so one
+// block's hood never leaves the slot of the points it covers.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "uh_device.hpp"
+#include "wagener_hull.h"
+
+namespace uh {
+
+constexpr int BLOCK = 256;       // threads per workgroup (4 waves)
+constexpr int LOG2_BLOCK = 8;
+constexpr int VMAX = 4096;       // corners a merge workgroup keeps in LDS
+
+struct TileItem {    // one tile of the tile pass
+  int64_t start;     // first point (absolute)
+  int32_t len;       // points, 1 .. T
+  int32_t set;
+  int32_t final_;    // 1 if this tile is its set's only tile
+  int32_t pad;
+};
+
+struct MergeItem {   // one workgroup of a merge pass
+  int64_t off;       // slot start = first child's slot start (absolute)
+  int32_t child0;    // first child in the previous level's arrays
+  int32_t nch;       // children, 2 .. F
+  int32_t set;
+  int32_t final_;    // 1 if this is its set's last merge
+};
+
+struct RunArgs {
+  const float2 *pts;
+  const int64_t *set_start;  // [S + 1]
+  float2 *ws_xy;             // [N] corner coordinates at their slots
+  int32_t *ws_idx;           // [N] set-relative index of each corner
+  int32_t *set_status;       // [S] worst data error seen (0 = none)
+  int32_t *out_idx;
+  int32_t *out_counts;
+  upper_hull_stats *stats;   // [S] or null
+  uint32_t flags;
+};
+
+// ------------------------------------------------------------ small helpers
+__device__ __forceinline__ int check_point(float2 v) {
+  // data contract: x in [0,1], y in [-1,1] (NaN fails), both on 2^-30 grid
+  if (!(v.x >= 0.0f && v.x <= 1.0f && v.y >= -1.0f && v.y <= 1.0f))
+    return UH_ERR_RANGE;
+  const float sx = v.x * 0x1p30f, sy = v.y * 0x1p30f;  // exact scalings
+  if (__builtin_rintf(sx) != sx || __builtin_rintf(sy) != sy) return UH_ERR_GRID;
+  return 0;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Adds the workgroup's orientation counters to stats[set] (if any).
+__device__ __forceinline__ void flush_stats(const RunArgs &A, int set,
+                                            const OrientCount &oc,
+                                            unsigned long long *sstat) {
+  const uint32_t e = wave_sum(oc.evals), f = wave_sum(oc.fallbacks);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&sstat[0], (unsigned long long)e);
+    atomicAdd(&sstat[1], (unsigned long long)f);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && A.stats) {
+    atomicAdd((unsigned long long *)&A.stats[set].orient_evals, sstat[0]);
+    atomicAdd((unsigned long long *)&A.stats[set].fallbacks, sstat[1]);
+  }
+}
+
+// Equal-x rule at the junction of two hoods (vertical closure): if P's last
+// and Q's first corner share x, only the higher survives (ties: P's, which
+// has the lower index).  Adjusts hp, or sets qs = 1 to skip Q's first.
+__device__ __forceinline__ void junction_rule(float2 plast, float2 qfirst,
+                                              int &hp, int &qs) {
+  if (plast.x == qfirst.x) {
+    if (qfirst.y > plast.y)
+      --hp;
+    else
+      qs = 1;
+  }
+}
+
+// ---------------------------------------------------------------- init
+__global__ void init_kernel(int32_t S, RunArgs A) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  A.set_status[s] = 0;
+  if (A.stats) {
+    A.stats[s].orient_evals = 0;
+    A.stats[s].fallbacks = 0;
+  }
+  if (A.set_start[s + 1] == A.set_start[s]) A.out_counts[s] = 0;
+}
+
+// ---------------------------------------------------------------- tiles
+template <int K>
+__global__ __launch_bounds__(BLOCK) void tile_kernel(RunArgs A,
+                                                     const TileItem *items,
+                                                     int32_t *cnt_out) {
+  constexpr int S = K + 1;  // LDS strip stride (odd: spreads banks)
+  __shared__ float2 sxy[BLOCK * S];
+  __shared__ uint16_t sid[BLOCK * S];
+  __shared__ int scnt[BLOCK];
+  __shared__ int2 sres[BLOCK / 2];
+  __shared__ int serr;
+  __shared__ unsigned long long sstat[2];
+
+  const TileItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
+  const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
+  const int64_t sstart = A.set_start[it.set];
+  if (tid == 0) {
+    serr = 0;
+    sstat[0] = sstat[1] = 0;
+  }
+
+  // ---- load: coalesced reads, scattered into per-lane strips in LDS
+  int err = 0;
+  const float2 *src = A.pts + it.start;
+#pragma unroll 4
+  for (int r = 0; r < K; ++r) {
+    const int e = tid + r * BLOCK;
+    if (e < it.len) {
+      const float2 v = src[e];
+      if (validate) err = min(err, check_point(v));
+      sxy[(e / K) * S + (e % K)] = v;
+    }
+  }
+  __syncthreads();
+  const int my_len = min(max(it.len - tid * K, 0), K);
+  float prevx = -1.0f;  // below every valid x
+  if (validate && my_len > 0) {
+    if (tid > 0)
+      prevx = sxy[(tid - 1) * S + (K - 1)].x;
+    else if (it.start > sstart)
+      prevx = A.pts[it.start - 1].x;
+  }
+  __syncthreads();
+
+  // ---- strip hood: monotone chain over this lane's K points, in place
+  OrientCount oc;
+  int cnt = 0;
+  if (my_len > 0) {
+    float2 *st = sxy + tid * S;
+    uint16_t *sl = sid + tid * S;
+    float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
+    int i = 0;
+    float2 r = st[0];
+    if (validate && r.x < prevx) err = min(err, UH_ERR_UNSORTED);
+    float px = r.x;
+    while (i < my_len) {
+      bool pop = false, skip = false;
+      if (cnt >= 1 && r.x == t1.x) {
+        if (r.y > t1.y)
+          pop = true;  // r hides the top (same x, higher)
+        else
+          skip = true;  // the top hides r (ties keep the lower index)
+      } else if (cnt >= 2) {
+        pop = orient_sign(t2, t1, r, oc, fe) >= 0;  // top on/below t2 -> r
+      }
+      if (pop) {
+        --cnt;
+        t1 = t2;
+        if (cnt >= 2) t2 = st[cnt - 2];
+      } else {
+        if (!skip) {
+          st[cnt] = r;
+          sl[cnt] = (uint16_t)(tid * K + i);
+          t2 = t1;
+          t1 = r;
+          ++cnt;
+        }
+        ++i;
+        if (i < my_len) {
+          r = st[i];
+          if (validate && r.x < px) err = min(err, UH_ERR_UNSORTED);
+          px = r.x;
+        }
+      }
+    }
+  }
+  scnt[tid] = cnt;
+  __syncthreads();
+
+  // ---- rounds of Wagener merges: block size K * 2^j -> K * 2^(j+1)
+#pragma unroll 1
+  for (int j = 0; j < LOG2_BLOCK; ++j) {
+    const int G = 2 << j;  // lanes per merge
+    const int m = tid >> (j + 1);
+    const int t = tid & (G - 1);
+    const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
+    float2 *P = sxy + lp * S;
+    float2 *Q = sxy + lq * S;
+    uint16_t *Pid = sid + lp * S;
+    const uint16_t *Qid = sid + lq * S;
+    int hp = scnt[lp];
+    const int hq = scnt[lq];
+    int qs = 0;
+    if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
+    const int hqe = hq - qs;
+    int a = hp - 1, b = 0;
+    const int L = G < 64 ? G : 64;
+    if (hp > 0 && hqe > 0 && t < L)
+      bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t,
+                                    a, b, oc, fe);
+    if (G > 64) {  // the search ran in the group's first wave: share it
+      if (t == 0) sres[m] = make_int2(a, b);
+      __syncthreads();
+      const int2 rr = sres[m];
+      a = rr.x;
+      b = rr.y;
+    }
+    // mam6, compacted: P[0..a] stays, Q[b..] moves to P[a+1..]
+    const int nsurv = hqe - b;
+    constexpr int PER = K / 2;  // Q holds <= K*2^j corners, G = 2^(j+1) lanes
+    float2 v[PER];
+    uint16_t vi[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = t + k * G;
+      if (e < nsurv) {
+        v[k] = Q[qs + b + e];
+        vi[k] = Qid[qs + b + e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = t + k * G;
+      if (e < nsurv) {
+        P[a + 1 + e] = v[k];
+        Pid[a + 1 + e] = vi[k];
+      }
+    }
+    if (t == 0) scnt[lp] = a + 1 + nsurv;
+    __syncthreads();
+  }
+
+  // ---- output
+  if (err) atomicMin(&serr, err);
+  flush_stats(A, it.set, oc, sstat);  // contains a barrier
+  const int hc = scnt[0];
+  const int rel0 = (int)(it.start - sstart);
+  if (it.final_) {
+    int32_t *dst = A.out_idx + sstart;
+    for (int k = tid; k < hc; k += BLOCK) dst[k] = rel0 + (int)sid[k];
+    if (tid == 0) A.out_counts[it.set] = serr ? serr : hc;
+  } else {
+    for (int k = tid; k < hc; k += BLOCK) {
+      A.ws_xy[it.start + k] = sxy[k];
+      A.ws_idx[it.start + k] = rel0 + (int)sid[k];
+    }
+    if (tid == 0) {
+      cnt_out[blockIdx.x] = hc;
+      if (serr) atomicMin(&A.set_status[it.set], serr);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- merges
+// Exclusive prefix sum of one value per thread over the workgroup.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) swave[w] = x;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int k = 0; k < BLOCK / 64; ++k) {
+    if (k < w) before += swave[k];
+    total += swave[k];
+  }
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(BLOCK) void merge_kernel(
+    RunArgs A, const MergeItem *items, const int64_t *child_off,
+    const int32_t *child_cnt, int32_t *cnt_out) {
+  __shared__ float2 bxy[2][VMAX];
+  __shared__ int32_t bid[2][VMAX];
+  __shared__ int choff[BLOCK + 1];
+  __shared__ int bcnt[BLOCK];
+  __shared__ int2 sres[BLOCK / 2];
+  __shared__ int swave[BLOCK / 64];
+  __shared__ int smax;
+  __shared__ unsigned long long sstat[2];
+
+  const MergeItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
+  const int nch = it.nch;
+  if (tid == 0) sstat[0] = sstat[1] = 0;
+
+  const int c = tid < nch ? child_cnt[it.child0 + tid] : 0;
+  int V;
+  const int o = block_exclusive_scan(c, swave, V);
+  choff[tid] = o;
+  bcnt[tid] = c;
+  if (tid == 0) choff[BLOCK] = V;
+  int npow = 1;
+  while (npow < nch) npow <<= 1;
+  OrientCount oc;
+  __syncthreads();
+
+  int hc;                  // final corner count
+  const float2 *res_xy;    // final corners (LDS or workspace)
+  const int32_t *res_id;
+  if (V <= VMAX) {
+    // ---- gather the children's corners into LDS, back to back
+    for (int v = tid; v < V; v += BLOCK) {
+      int lo = 0, hi = nch - 1;  // last k with choff[k] <= v
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (choff[mid] <= v)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const int64_t g = child_off[it.child0 + lo] + (v - choff[lo]);
+      bxy[0][v] = A.ws_xy[g];
+      bid[0][v] = A.ws_idx[g];
+    }
+    __syncthreads();
+    int cur = 0;
+#pragma unroll 1
+    for (int j = 0; (1 << j) < nch; ++j) {
+      const int M = npow >> (j + 1);  // merges at this round
+      const int G = BLOCK / M;
+      const int m = tid / G, t = tid % G;
+      const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
+      const float2 *sxy = bxy[cur];
+      const int32_t *sid = bid[cur];
+      float2 *dxy = bxy[cur ^ 1];
+      int32_t *did = bid[cur ^ 1];
+      int a = -1, b = 0, hp = 0, hqe = 0, qs = 0, op = 0, oq = 0;
+      if (lp < nch) {
+        op = choff[lp];
+        hp = bcnt[lp];
+        int hq = 0;
+        if (lq < nch) {
+          oq = choff[lq];
+          hq = bcnt[lq];
+        }
+        if (hp > 0 && hq > 0) junction_rule(sxy[op + hp - 1], sxy[oq], hp, qs);
+        hqe = hq - qs;
+        a = hp - 1;
+        const int L = G < 64 ? G : 64;
+        if (hp > 0 && hqe > 0 && t < L)
+          bridge_search<const float2 *>(sxy + op, hp, sxy + oq + qs, hqe, L, t,
+                                        (tid & 63) - t, a, b, oc, fe);
+      }
+      if (G > 64) {
+        if (t == 0) sres[m] = make_int2(a, b);
+        __syncthreads();
+        const int2 rr = sres[m];
+        a = rr.x;
+        b = rr.y;
+      }
+      if (lp < nch) {
+        const int nsurv = hqe - b;
+        for (int e = t; e <= a; e += G) {
+          dxy[op + e] = sxy[op + e];
+          did[op + e] = sid[op + e];
+        }
+        for (int e = t; e < nsurv; e += G) {
+          dxy[op + a + 1 + e] = sxy[oq + qs + b + e];
+          did[op + a + 1 + e] = sid[oq + qs + b + e];
+        }
+        if (t == 0) bcnt[lp] = a + 1 + nsurv;
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+    hc = bcnt[0];
+    res_xy = bxy[cur];
+    res_id = bid[cur];
+  } else {
+    // ---- too large for LDS: the same rounds in place in the workspace
+#pragma unroll 1
+    for (int j = 0; (1 << j) < nch; ++j) {
+      const int M = npow >> (j + 1);
+      const int G = BLOCK / M;
+      const int m = tid / G, t = tid % G;
+      const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
+      int a = -1, b = 0, hp = 0, hqe = 0, qs = 0;
+      float2 *P = nullptr, *Q = nullptr;
+      int32_t *Pid = nullptr, *Qid = nullptr;
+      if (tid == 0) smax = 0;
+      if (lp < nch && lq < nch) {
+        const int64_t op = child_off[it.child0 + lp], oq = child_off[it.child0 + lq];
+        P = A.ws_xy + op;
+        Q = A.ws_xy + oq;
+        Pid = A.ws_idx + op;
+        Qid = A.ws_idx + oq;
+        hp = bcnt[lp];
+        const int hq = bcnt[lq];
+        if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
+        hqe = hq - qs;
+        a = hp - 1;
+        const int L = G < 64 ? G : 64;
+        if (hp > 0 && hqe > 0 && t < L)
+          bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t,
+                                        a, b, oc, fe);
+      }
+      __syncthreads();  // smax cleared, and searches done reading
+      if (G > 64) {
+        if (t == 0) sres[m] = make_int2(a, b);
+        __syncthreads();
+        const int2 rr = sres[m];
+        a = rr.x;
+        b = rr.y;
+      }
+      const bool active = lp < nch && lq < nch;
+      const int nsurv = active ? hqe - b : 0;
+      const int chunks = (nsurv + G - 1) / G;
+      if (t == 0 && active) atomicMax(&smax, chunks);
+      __syncthreads();
+      const int maxchunks = smax;
+      // left shift Q[b..] to P[a+1..]: destination never passes the source,
+      // so reading chunk c before anyone writes it keeps every value intact
+      for (int ch = 0; ch < maxchunks; ++ch) {
+        const int e = ch * G + t;
+        float2 v = make_float2(0.f, 0.f);
+        int32_t vi = 0;
+        const bool mine = e < nsurv;
+        if (mine) {
+          v = Q[qs + b + e];
+          vi = Qid[qs + b + e];
+        }
+        __syncthreads();
+        if (mine) {
+          P[a + 1 + e] = v;
+          Pid[a + 1 + e] = vi;
+        }
+        __syncthreads();
+      }
+      if (t == 0 && active) bcnt[lp] = a + 1 + nsurv;
+      __syncthreads();
+    }
+    hc = bcnt[0];
+    res_xy = A.ws_xy + it.off;
+    res_id = A.ws_idx + it.off;
+  }
+
+  flush_stats(A, it.set, oc, sstat);  // contains a barrier
+  if (it.final_) {
+    const int64_t sstart = A.set_start[it.set];
+    int32_t *dst = A.out_idx + sstart;
+    for (int k = tid; k < hc; k += BLOCK) dst[k] = res_id[k];
+    if (tid == 0) {
+      const int st = A.set_status[it.set];
+      A.out_counts[it.set] = st ? st : hc;
+    }
+  } else {
+    if (V <= VMAX) {
+      for (int k = tid; k < hc; k += BLOCK) {
+        A.ws_xy[it.off + k] = res_xy[k];
+        A.ws_idx[it.off + k] = res_id[k];
+      }
+    }
+    if (tid == 0) cnt_out[blockIdx.x] = hc;
+  }
+}
+
+// ---------------------------------------------------------------- probes
+__global__ void bridge_kernel(const float2 *P, int hp, const float2 *Q, int hq,
+                              int L, int32_t *out_ab) {
+  const int t = threadIdx.x;
+  OrientCount oc;
+  int a = -1, b = -1;
+  if (t < L) bridge_search<const float2 *>(P, hp, Q, hq, L, t, 0, a, b, oc, false);
+  if (t == 0) {
+    out_ab[0] = a;
+    out_ab[1] = b;
+  }
+}
+
+__global__ void orient_kernel(const float2 *a, const float2 *b, const float2 *c,
+                              int64_t m, int8_t *out, uint8_t *fb, int force) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  OrientCount oc;
+  out[i] = (int8_t)orient_sign(a[i], b[i], c[i], oc, force != 0);
+  if (fb) fb[i] = (uint8_t)(oc.fallbacks != 0);
+}
+
+}  // namespace uh
+
+// ====================================================================== host
+using namespace uh;
+
+struct upper_hull_plan {
+  int device = 0;
+  int32_t S = 0;
+  int64_t N = 0;
+  int K = 16, T = 4096, F = 256;
+  uint32_t flags = 0;
+  int32_t ntiles = 0;
+  std::vector<int32_t> pass_items;  // merge items per pass
+  // device memory
+  int64_t *d_set_start = nullptr;
+  TileItem *d_tiles = nullptr;
+  int64_t *d_tile_off = nullptr;
+  int32_t *d_cnt0 = nullptr;
+  std::vector<MergeItem *> d_items;
+  std::vector<int64_t *> d_off;   // per pass: item slot offsets
+  std::vector<int32_t *> d_cnt;   // per pass: item corner counts
+  float2 *ws_xy = nullptr;
+  int32_t *ws_idx = nullptr;
+  int32_t *set_status = nullptr;
+  // graph cache: (points, out_idx, out_counts, stats) -> exec
+  std::map<std::tuple<const void *, void *, void *, void *>, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t probe_before = nullptr, probe_after = nullptr;
+  std::mutex mu;
+};
+
+namespace {
+
+template <class T>
+int dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T)) == hipSuccess ? UH_OK : UH_ERR_ALLOC;
+}
+
+template <class T>
+int upload(T *dst, const std::vector<T> &src) {
+  if (src.empty()) return UH_OK;
+  return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) ==
+                 hipSuccess
+             ? UH_OK
+             : UH_ERR_HIP;
+}
+
+void free_plan_memory(upper_hull_plan *p) {
+  hipFree(p->d_set_start);
+  hipFree(p->d_tiles);
+  hipFree(p->d_tile_off);
+  hipFree(p->d_cnt0);
+  for (auto *q : p->d_items) hipFree(q);
+  for (auto *q : p->d_off) hipFree(q);
+  for (auto *q : p->d_cnt) hipFree(q);
+  hipFree(p->ws_xy);
+  hipFree(p->ws_idx);
+  hipFree(p->set_status);
+  for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+}
+
+int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
+  {
+    const int nb = (p->S + 255) / 256;
+    hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, stream, p->S, A);
+  }
+  if (p->ntiles > 0) {
+    const dim3 grid(p->ntiles), blk(BLOCK);
+    if (p->probe_before && hipEventRecord(p->probe_before, stream) != hipSuccess)
+      return UH_ERR_HIP;
+    switch (p->K) {
+      case 4: hipLaunchKernelGGL(tile_kernel<4>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
+      case 8: hipLaunchKernelGGL(tile_kernel<8>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
+      case 16: hipLaunchKernelGGL(tile_kernel<16>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
+      case 32: hipLaunchKernelGGL(tile_kernel<32>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
+      default: return UH_ERR_ARG;
+    }
+    if (p->probe_after && hipEventRecord(p->probe_after, stream) != hipSuccess)
+      return UH_ERR_HIP;
+  }
+  for (size_t ps = 0; ps < p->pass_items.size(); ++ps) {
+    const int64_t *coff = ps == 0 ? p->d_tile_off : p->d_off[ps - 1];
+    const int32_t *ccnt = ps == 0 ? p->d_cnt0 : p->d_cnt[ps - 1];
+    hipLaunchKernelGGL(merge_kernel, dim3(p->pass_items[ps]), dim3(BLOCK), 0, stream, A,
+                       p->d_items[ps], coff, ccnt, p->d_cnt[ps]);
+  }
+  return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+std::mutex g_cache_mu;
+std::map<std::pair<int, int64_t>, upper_hull_plan *> g_single_plans;
+
+}  // namespace
+
+extern "C" {
+
+const char *upper_hull_status_string(int status) {
+  switch (status) {
+    case UH_OK: return "ok";
+    case UH_ERR_ARG: return "invalid argument";
+    case UH_ERR_ALLOC: return "device allocation failed";
+    case UH_ERR_HIP: return "HIP runtime error";
+    case UH_ERR_CAPTURE: return "plan creation not allowed during stream capture";
+    case UH_ERR_UNSORTED: return "data error: x not non-decreasing";
+    case UH_ERR_RANGE: return "data error: coordinate out of range or not finite";
+    case UH_ERR_GRID: return "data error: coordinate not on the 2^-30 grid";
+    default: return status >= 0 ? "ok (count)" : "unknown status";
+  }
+}
+
+int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
+                           const upper_hull_config *config,
+                           upper_hull_plan **out_plan) {
+  if (!set_offsets || num_sets < 1 || !out_plan) return UH_ERR_ARG;
+  *out_plan = nullptr;
+  if (set_offsets[0] != 0) return UH_ERR_ARG;
+  for (int32_t s = 0; s < num_sets; ++s) {
+    if (set_offsets[s + 1] < set_offsets[s]) return UH_ERR_ARG;
+    if (set_offsets[s + 1] - set_offsets[s] > INT32_MAX) return UH_ERR_ARG;
+  }
+  int K = 16, F = 256;
+  uint32_t flags = 0;
+  if (config) {
+    if (config->strip) K = config->strip;
+    if (config->fan_in) F = config->fan_in;
+    flags = config->flags;
+  }
+  if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
+  if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
+
+  auto *p = new upper_hull_plan();
+  hipGetDevice(&p->device);
+  p->S = num_sets;
+  p->N = set_offsets[num_sets];
+  p->K = K;
+  p->T = BLOCK * K;
+  p->F = F;
+  p->flags = flags;
+
+  // level 0: tiles; then merge passes of fan-in F until one hood per set
+  std::vector<TileItem> tiles;
+  std::vector<int64_t> tile_off;
+  std::vector<int32_t> first(num_sets), count(num_sets);  // blocks per set
+  for (int32_t s = 0; s < num_sets; ++s) {
+    const int64_t n = set_offsets[s + 1] - set_offsets[s];
+    const int64_t nt = (n + p->T - 1) / p->T;
+    first[s] = (int32_t)tiles.size();
+    count[s] = (int32_t)nt;
+    for (int64_t t = 0; t < nt; ++t) {
+      TileItem it;
+      it.start = set_offsets[s] + t * p->T;
+      it.len = (int32_t)std::min<int64_t>(p->T, n - t * p->T);
+      it.set = s;
+      it.final_ = nt == 1;
+      it.pad = 0;
+      tiles.push_back(it);
+      tile_off.push_back(it.start);
+    }
+  }
+  p->ntiles = (int32_t)tiles.size();
+  std::vector<int64_t> prev_off = tile_off;
+  std::vector<std::vector<MergeItem>> passes;
+  for (;;) {
+    std::vector<MergeItem> items;
+    std::vector<int32_t> nfirst(num_sets), ncount(num_sets);
+    for (int32_t s = 0; s < num_sets; ++s) {
+      nfirst[s] = (int32_t)items.size();
+      ncount[s] = 0;
+      if (count[s] <= 1) continue;
+      const int32_t nitems = (count[s] + F - 1) / F;
+      for (int32_t i = 0; i < nitems; ++i) {
+        MergeItem m;
+        m.child0 = first[s] + i * F;
+        m.nch = std::min(F, count[s] - i * F);
+        m.off = prev_off[m.child0];
+        m.set = s;
+        m.final_ = nitems == 1;
+        items.push_back(m);
+      }
+      ncount[s] = nitems;
+    }
+    if (items.empty()) break;
+    std::vector<int64_t> off(items.size());
+    for (size_t i = 0; i < items.size(); ++i) off[i] = items[i].off;
+    passes.push_back(items);
+    prev_off = off;
+    first = nfirst;
+    // sets finished in this pass keep count 1 -> no further items
+    for (int32_t s = 0; s < num_sets; ++s) count[s] = ncount[s];
+  }
+
+  int rc = UH_OK;
+  std::vector<int64_t> so(set_offsets, set_offsets + num_sets + 1);
+  rc = rc ? rc : dalloc(&p->d_set_start, so.size());
+  rc = rc ? rc : upload(p->d_set_start, so);
+  rc = rc ? rc : dalloc(&p->d_tiles, tiles.size());
+  rc = rc ? rc : upload(p->d_tiles, tiles);
+  rc = rc ? rc : dalloc(&p->d_tile_off, tile_off.size());
+  rc = rc ? rc : upload(p->d_tile_off, tile_off);
+  rc = rc ? rc : dalloc(&p->d_cnt0, tiles.size());
+  for (auto &items : passes) {
+    if (rc) break;
+    MergeItem *di = nullptr;
+    int64_t *doff = nullptr;
+    int32_t *dcnt = nullptr;
+    std::vector<int64_t> off(items.size());
+    for (size_t i = 0; i < items.size(); ++i) off[i] = items[i].off;
+    rc = rc ? rc : dalloc(&di, items.size());
+    rc = rc ? rc : upload(di, items);
+    rc = rc ? rc : dalloc(&doff, items.size());
+    rc = rc ? rc : upload(doff, off);
+    rc = rc ? rc : dalloc(&dcnt, items.size());
+    p->d_items.push_back(di);
+    p->d_off.push_back(doff);
+    p->d_cnt.push_back(dcnt);
+    p->pass_items.push_back((int32_t)items.size());
+  }
+  rc = rc ? rc : dalloc(&p->ws_xy, (size_t)p->N);
+  rc = rc ? rc : dalloc(&p->ws_idx, (size_t)p->N);
+  rc = rc ? rc : dalloc(&p->set_status, (size_t)num_sets);
+  if (rc) {
+    free_plan_memory(p);
+    delete p;
+    return rc;
+  }
+  *out_plan = p;
+  return UH_OK;
+}
+
+int upper_hull_plan_launches(const upper_hull_plan *plan) {
+  if (!plan) return UH_ERR_ARG;
+  return 1 + (plan->ntiles > 0) + (int)plan->pass_items.size();
+}
+
+int upper_hull_plan_set_probe(upper_hull_plan *plan, hipEvent_t before,
+                              hipEvent_t after) {
+  if (!plan || (plan->flags & UH_FLAG_GRAPH) || (!before) != (!after)) return UH_ERR_ARG;
+  plan->probe_before = before;
+  plan->probe_after = after;
+  return UH_OK;
+}
+
+int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_idx,
+                        int32_t *out_counts, upper_hull_stats *stats,
+                        hipStream_t stream) {
+  if (!p || !out_counts || (p->N > 0 && (!points || !out_idx))) return UH_ERR_ARG;
+  if (((uintptr_t)points & 7u) != 0) return UH_ERR_ARG;
+  RunArgs A;
+  A.pts = (const float2 *)points;
+  A.set_start = p->d_set_start;
+  A.ws_xy = p->ws_xy;
+  A.ws_idx = p->ws_idx;
+  A.set_status = p->set_status;
+  A.out_idx = out_idx;
+  A.out_counts = out_counts;
+  A.stats = stats;
+  A.flags = p->flags;
+  if (!(p->flags & UH_FLAG_GRAPH)) return enqueue_run(p, A, stream);
+
+  std::lock_guard<std::mutex> lock(p->mu);
+  auto key = std::make_tuple((const void *)points, (void *)out_idx, (void *)out_counts,
+                             (void *)stats);
+  auto itg = p->graphs.find(key);
+  if (itg == p->graphs.end()) {
+    if (!p->cap_stream &&
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return UH_ERR_HIP;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+      return UH_ERR_HIP;
+    const int rc = enqueue_run(p, A, p->cap_stream);
+    if (hipStreamEndCapture(p->cap_stream, &g) != hipSuccess || rc) {
+      if (g) hipGraphDestroy(g);
+      return rc ? rc : UH_ERR_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ie != hipSuccess) return UH_ERR_HIP;
+    itg = p->graphs.emplace(key, ex).first;
+  }
+  return hipGraphLaunch(itg->second, stream) == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+void upper_hull_plan_destroy(upper_hull_plan *plan) {
+  if (!plan) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(plan->device);
+  hipDeviceSynchronize();
+  free_plan_memory(plan);
+  hipSetDevice(cur);
+  delete plan;
+}
+
+int upper_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_count,
+               hipStream_t stream) {
+  if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx)))
+    return UH_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
+  upper_hull_plan *p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto key = std::make_pair(dev, n);
+    auto it = g_single_plans.find(key);
+    if (it != g_single_plans.end()) {
+      p = it->second;
+    } else {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
+      if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
+      if (g_single_plans.size() >= 8) {  // bounded cache: drop the oldest
+        upper_hull_plan_destroy(g_single_plans.begin()->second);
+        g_single_plans.erase(g_single_plans.begin());
+      }
+      const int64_t off[2] = {0, n};
+      const int rc = upper_hull_plan_create(off, 1, nullptr, &p);
+      if (rc) return rc;
+      g_single_plans.emplace(key, p);
+    }
+  }
+  return upper_hull_plan_run(p, points, out_idx, out_count, nullptr, stream);
+}
+
+int upper_hull_bridge(const float *P, int32_t hp, const float *Q, int32_t hq,
+                      int32_t lanes, int32_t *out_ab, hipStream_t stream) {
+  if (!P || !Q || !out_ab || hp < 1 || hq < 1) return UH_ERR_ARG;
+  if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1))) return UH_ERR_ARG;
+  hipLaunchKernelGGL(bridge_kernel, dim3(1), dim3(64), 0, stream, (const float2 *)P, hp,
+                     (const float2 *)Q, hq, lanes, out_ab);
+  return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+int upper_hull_orient(const float *a, const float *b, const float *c, int64_t m,
+                      int8_t *out_sign, uint8_t *out_fallback, int32_t force_fallback,
+                      hipStream_t stream) {
+  if (m < 0 || (m > 0 && (!a || !b || !c || !out_sign))) return UH_ERR_ARG;
+  if (m == 0) return UH_OK;
+  const int64_t nb = (m + 255) / 256;
+  if (nb > INT32_MAX) return UH_ERR_ARG;
+  hipLaunchKernelGGL(orient_kernel, dim3((unsigned)nb), dim3(256), 0, stream,
+                     (const float2 *)a, (const float2 *)b, (const float2 *)c, m, out_sign,
+                     out_fallback, force_fallback);
+  return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+}  // extern "C"
