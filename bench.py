@@ -100,6 +100,12 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--compare-plain", action="store_true",
+                    help="also time the plain per-set method (one plan per set, launched "
+                         "set by set from the host) against the batched plan")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (scale reference for "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -122,6 +128,14 @@ def main():
         f"in {time.perf_counter() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("[bench] calibration copy: 2 x 1 GiB device-to-device")
     pts = torch.from_numpy(pts_np).to(dev)
     N, S = len(pts_np), len(off) - 1
     flags = uh.UH_FLAG_GRAPH if args.graph else 0
@@ -172,6 +186,34 @@ def main():
             ev.destroy(a)
             ev.destroy(b)
 
+    plain = None
+    if args.compare_plain:
+        log(f"[bench] plain per-set method: {S} plans ...")
+        plans = [uh.upper_hull_plan_create([0, int(off[s + 1] - off[s])], strip=args.strip)
+                 for s in range(S)]
+        views = [(pts[off[s]:off[s + 1]], out_idx[off[s]:max(off[s + 1], off[s] + 1)],
+                  out_cnt[s:s + 1]) for s in range(S)]
+        for s in range(S):  # warm-up
+            plans[s].run(*views[s])
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 5))
+        t0 = time.perf_counter()
+        start.record()
+        for _ in range(reps):
+            for s in range(S):
+                plans[s].run(*views[s])
+        end.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        gpu_ms = start.elapsed_time(end) / reps
+        plain_ok = bool(np.array_equal(out_cnt.cpu().numpy(), cnt_np))
+        for pl in plans:
+            pl.close()
+        plain = {"ms_per_step": round(gpu_ms, 3), "host_wall_ms_per_step": round(wall * 1e3, 3),
+                 "points_per_s": round(N / (gpu_ms * 1e-3), 1),
+                 "batched_speedup": round(gpu_ms / ms_step, 2), "same_counts": plain_ok}
+        log(f"[bench] plain: {gpu_ms:.3f} ms/step -> batched is {gpu_ms / ms_step:.2f}x faster")
+
     h_total = int(cnt_np.sum())
     alg_tile = 8.0 * N  # every point read once (float2)
     roofline = None
@@ -212,6 +254,7 @@ def main():
                    "matches_oracle": checked},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "plain_per_set": plain,
     }
     print(json.dumps(line), flush=True)
     plan.close()

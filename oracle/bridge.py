@@ -102,6 +102,19 @@ def bridge(P, Q):
     return min(i for i, _ in valid), max(j for _, j in valid)
 
 
+def survivors(P, Q):
+    """Corner-wise form of the merge, by definition of a strict corner:
+    P corner i stays iff i == 0 or every Q corner is strictly below the line
+    through P[i-1] and P[i]; Q corner j stays iff j == last or every P corner
+    is strictly below the line through Q[j] and Q[j+1].  Returns the kept
+    index sets (they are P[0..a] and Q[b..] for the bridge (a, b))."""
+    keep_p = [i for i in range(len(P))
+              if i == 0 or all(det(P[i - 1], P[i], q) < 0 for q in Q)]
+    keep_q = [j for j in range(len(Q))
+              if j == len(Q) - 1 or all(det(Q[j], Q[j + 1], p) < 0 for p in P)]
+    return keep_p, keep_q
+
+
 def merge(P, Q):
     """Corner list of H(P u Q): P[0..a] followed by Q[b..]."""
     a, b = bridge(P, Q)

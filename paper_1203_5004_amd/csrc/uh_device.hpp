@@ -116,10 +116,23 @@ __device__ __forceinline__ int f_classify(float2 q, PT P, int i, int hp,
   return EQUAL;
 }
 
-// lo + floor(k * span / div) without 32-bit overflow for large spans.
-__device__ __forceinline__ int sample_at(int lo, int k, int span, int div) {
-  if (span < (1 << 27)) return lo + (k * span) / div;
-  return lo + (int)(((long long)k * (long long)span) / div);
+// Sample positions.  Correctness of the searches below only needs samples
+// that are nondecreasing in the lane index and stay inside [lo, lo + span);
+// they are computed without integer division (which costs dozens of
+// instructions on the GPU):
+//   P samples: lo + floor(k * span / d1) with d1 a power of two (a shift);
+//   Q samples: lo + floor(span * k * c), c = (1 - 2^-22) / (d2 + 1) < 1 / (d2 + 1),
+//              in FP32 while span < 2^24 (exact conversion), else in FP64.
+// Every lane evaluates the same expression for the same k, so the bounds
+// recomputed from the ballots match the positions the lanes sampled.
+__device__ __forceinline__ int psample(int lo, int k, int span, int lg1) {
+  if (span < (1 << 26)) return lo + ((k * span) >> lg1);
+  return lo + (int)(((long long)k * (long long)span) >> lg1);
+}
+
+__device__ __forceinline__ int qsample(int lo, int k, int span, float c, double cd) {
+  if (span < (1 << 24)) return lo + (int)((float)span * ((float)k * c));
+  return lo + (int)((double)span * ((double)k * cd));
 }
 
 // Gather the bits of the d1 sub-group leaders (lanes base + k * d2) of a
@@ -164,30 +177,32 @@ __device__ __forceinline__ void bridge_search(PT P, int hp, PT Q, int hq,
   const int y = t & (d2 - 1);
   const int sub = base + x * d2;
   const uint32_t sub_mask = (1u << d2) - 1u;
+  const float c = (1.0f - 0x1p-22f) / (float)(d2 + 1);
+  const double cd = (1.0 - 0x1p-40) / (double)(d2 + 1);
 
   int plo = 0, phi = hp;
   for (;;) {
     const int span = phi - plo;
-    const int i = sample_at(plo, x, span, d1);
+    const int i = psample(plo, x, span, lg1);
     const float2 p = P[i];
     // mam1/mam2: tangent corner of p on Q, in [lo, hi)
     int lo = 0, hi = hq;
     while (hi - lo > 1) {
       const int sp = hi - lo;
-      const int s = sample_at(lo, y + 1, sp, d2 + 1);
+      const int s = qsample(lo, y + 1, sp, c, cd);
       const int gv = g_classify(p, Q, s, hq, cnt, fe);
       const uint32_t ml = (uint32_t)(__ballot(gv == LOW) >> sub) & sub_mask;
       const uint32_t me = (uint32_t)(__ballot(gv == EQUAL) >> sub) & sub_mask;
       const uint32_t mh = (uint32_t)(__ballot(gv == HIGH) >> sub) & sub_mask;
       if (me) {
-        lo = sample_at(lo, __builtin_ctz(me) + 1, sp, d2 + 1);
+        lo = qsample(lo, __builtin_ctz(me) + 1, sp, c, cd);
         hi = lo + 1;
         break;
       }
       const int nl = __builtin_popcount(ml);
       const int nh = __builtin_popcount(mh);
-      const int nlo = nl ? sample_at(lo, nl, sp, d2 + 1) + 1 : lo;
-      const int nhi = nh ? sample_at(lo, d2 - nh + 1, sp, d2 + 1) : hi;
+      const int nlo = nl ? qsample(lo, nl, sp, c, cd) + 1 : lo;
+      const int nhi = nh ? qsample(lo, d2 - nh + 1, sp, c, cd) : hi;
       lo = nlo;
       hi = nhi;
     }
@@ -202,14 +217,14 @@ __device__ __forceinline__ void bridge_search(PT P, int hp, PT Q, int hq,
     const uint32_t fh = leader_bits(bh, base, d1, d2);
     if (feq) {
       const int k = __builtin_ctz(feq);
-      out_a = sample_at(plo, k, span, d1);
+      out_a = psample(plo, k, span, lg1);
       out_b = __shfl(jt, base + k * d2, 64);
       return;
     }
     const int nl = __builtin_popcount(fl);
     const int nh = __builtin_popcount(fh);
-    const int nplo = nl ? sample_at(plo, nl - 1, span, d1) + 1 : plo;
-    const int nphi = nh ? sample_at(plo, d1 - nh, span, d1) : phi;
+    const int nplo = nl ? psample(plo, nl - 1, span, lg1) + 1 : plo;
+    const int nphi = nh ? psample(plo, d1 - nh, span, lg1) : phi;
     if (nphi <= nplo) {  // only on an inconsistent (invalid-data) predicate
       out_a = nplo < 0 ? 0 : (nplo >= hp ? hp - 1 : nplo);
       out_b = 0;
@@ -217,6 +232,164 @@ __device__ __forceinline__ void bridge_search(PT P, int hp, PT Q, int hq,
     }
     plo = nplo;
     phi = nphi;
+  }
+}
+
+// Orders LDS accesses of one wave: all lanes' earlier accesses are done
+// before any later one (a wave runs in lockstep; this stops the compiler
+// from moving LDS operations across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Moves n (x, y, id) records from src to dst inside one LDS region, with the
+// G lanes of one group (t = lane in group), correct for overlapping ranges:
+// each chunk is read by all lanes before any lane writes it, and chunks go
+// left to right for a move to the left, right to left for a move right.
+template <class ID>
+__device__ __forceinline__ void group_move(float2 *xy, ID *id, int src, int dst,
+                                           int n, int lgG, int t) {
+  if (n <= 0 || src == dst) return;
+  const int G = 1 << lgG;
+  const int nch = (n + G - 1) >> lgG;
+  for (int k = 0; k < nch; ++k) {
+    const int c = dst < src ? k : nch - 1 - k;
+    const int e = (c << lgG) + t;
+    const bool mine = e < n;
+    float2 v = make_float2(0.f, 0.f);
+    ID vi = 0;
+    if (mine) {
+      v = xy[src + e];
+      vi = id[src + e];
+    }
+    wave_sync();
+    if (mine) {
+      xy[dst + e] = v;
+      id[dst + e] = vi;
+    }
+    wave_sync();
+  }
+}
+
+// Hoods at most this long are merged by the corner test instead of the
+// sampled search.
+constexpr int SMALL_HOOD = 8;
+
+// Merge (match-and-merge, mam1-mam6) of two adjacent hoods stored in one LDS
+// region: P = [bp, bp + hp) and Q = [bq, bq + hq), bp + hp <= bq, run by the
+// G <= 64 lanes of one group of one wave.  The merged hood
+// P[0..a] ++ Q[b..] is made contiguous by moving the shorter of the two kept
+// parts next to the other; returns its start nb and length nc.
+// Also applies the vertical-closure rule at the junction: if P's last and
+// Q's first corner share x, only the higher survives (ties: P's, the lower
+// index).
+template <class ID>
+__device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
+                                             int bq, int hq, int lgG, int t, int gbase,
+                                             int &nb, int &nc, OrientCount &oc,
+                                             bool fe) {
+  const int G = 1 << lgG;
+  nb = bp;
+  nc = hp;
+  if (hq == 0) return;
+  if (hp > 0) {
+    const float2 pl = xy[bp + hp - 1], qf = xy[bq];
+    if (pl.x == qf.x) {
+      if (qf.y > pl.y)
+        --hp;
+      else {
+        ++bq;
+        --hq;
+      }
+    }
+  }
+  if (hp == 0) {
+    nb = bq;
+    nc = hq;
+    return;
+  }
+  if (hq == 0) {
+    nc = hp;
+    return;
+  }
+  int a = hp - 1, b = 0;
+  if (hp <= SMALL_HOOD && hq <= SMALL_HOOD) {
+    // Small hoods: each corner decides whether it stays, by the definition of
+    // a strict corner of the union -- P[i] stays iff i == 0 or every Q corner
+    // is strictly below the line P[i-1] -> P[i]; Q[j] stays iff j is last or
+    // every P corner is strictly below the line Q[j] -> Q[j+1].  The kept
+    // corners are exactly P[0..a] and Q[b..] for the bridge (a, b), so
+    // counting them gives both ends.  Lane t takes corners t, t + G, ...
+    int nkp = 0, nkq = 0;
+    for (int c0 = 0; c0 < hp + hq; c0 += G) {
+      const int c = c0 + t;
+      bool keep = false;
+      if (c < hp) {
+        keep = true;
+        if (c > 0) {
+          const float2 p0 = xy[bp + c - 1], p1 = xy[bp + c];
+          for (int k = 0; k < hq && keep; ++k)
+            keep = orient_sign(p0, p1, xy[bq + k], oc, fe) < 0;
+        }
+      } else if (c < hp + hq) {
+        const int j = c - hp;
+        keep = true;
+        if (j + 1 < hq) {
+          const float2 q0 = xy[bq + j], q1 = xy[bq + j + 1];
+          for (int k = 0; k < hp && keep; ++k)
+            keep = orient_sign(q0, q1, xy[bp + k], oc, fe) < 0;
+        }
+      }
+      const uint64_t m = (__ballot(keep) >> gbase) & (G == 64 ? ~0ull : ((1ull << G) - 1ull));
+      // lanes of this round holding P corners: t < hp - c0
+      const int np_lanes = min(max(hp - c0, 0), G);
+      const uint64_t pm = np_lanes == 64 ? ~0ull : ((1ull << np_lanes) - 1ull);
+      nkp += __builtin_popcountll(m & pm);
+      nkq += __builtin_popcountll(m & ~pm);
+    }
+    a = nkp - 1;
+    b = hq - nkq;
+  } else {
+    bridge_search<const float2 *>(xy + bp, hp, xy + bq, hq, G, t, gbase, a, b, oc, fe);
+  }
+  const int np = a + 1, nq = hq - b;
+  nc = np + nq;
+  if (np <= nq) {  // P's kept corners move right, to end just before Q[b]
+    nb = bq + b - np;
+    group_move(xy, id, bp, nb, np, lgG, t);
+  } else {         // Q's kept corners move left, to follow P[a]
+    nb = bp;
+    group_move(xy, id, bq + b, bp + np, nq, lgG, t);
+  }
+}
+
+// Rounds of Wagener merges over nleaf <= 64 leaf hoods, run by one whole
+// wave: blk[0..nleaf) hold (base, count) of consecutive, x-adjacent,
+// non-empty hoods in the LDS arrays xy / id.  Round j joins blocks of 2^j
+// leaves; with M merges in a round each merge gets 64 / M lanes (the
+// paper's d1 x d2 block).  The hood of all leaves ends in blk[0].
+template <class ID>
+__device__ __forceinline__ void wave_rounds(float2 *xy, ID *id, int2 *blk, int nleaf,
+                                            OrientCount &oc, bool fe) {
+  const int lane = threadIdx.x & 63;
+  int lgn = 0;
+  while ((1 << lgn) < nleaf) ++lgn;
+#pragma unroll 1
+  for (int j = 0; j < lgn; ++j) {
+    const int lgG = 6 - lgn + j + 1;
+    const int t = lane & ((1 << lgG) - 1);
+    const int lp = (lane >> lgG) << (j + 1);
+    const int lq = lp + (1 << j);
+    if (lq < nleaf) {
+      const int2 P = blk[lp], Q = blk[lq];
+      int nb, nc;
+      merge_blocks(xy, id, P.x, P.y, Q.x, Q.y, lgG, t, lane - t, nb, nc, oc, fe);
+      wave_sync();
+      if (t == 0) blk[lp] = make_int2(nb, nc);
+    }
+    wave_sync();
   }
 }
 

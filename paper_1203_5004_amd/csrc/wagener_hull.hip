@@ -43,8 +43,7 @@
 namespace uh {
 
 constexpr int BLOCK = 256;       // threads per workgroup (4 waves)
-constexpr int LOG2_BLOCK = 8;
-constexpr int VMAX = 4096;       // corners a merge workgroup keeps in LDS
+constexpr int VMAX = 8192;       // corners a merge workgroup keeps in LDS
 
 struct TileItem {    // one tile of the tile pass
   int64_t start;     // first point (absolute)
@@ -76,12 +75,12 @@ struct RunArgs {
 
 // ------------------------------------------------------------ small helpers
 __device__ __forceinline__ int check_point(float2 v) {
-  // data contract: x in [0,1], y in [-1,1] (NaN fails), both on 2^-30 grid
-  if (!(v.x >= 0.0f && v.x <= 1.0f && v.y >= -1.0f && v.y <= 1.0f))
+  // data contract: x in [0,1], y in [-1,1] (NaN fails both), both on the
+  // 2^-30 grid: scaling by 2^30 is exact, and then no fraction may remain
+  if (!(__builtin_fabsf(v.x - 0.5f) <= 0.5f && __builtin_fabsf(v.y) <= 1.0f))
     return UH_ERR_RANGE;
-  const float sx = v.x * 0x1p30f, sy = v.y * 0x1p30f;  // exact scalings
-  if (__builtin_rintf(sx) != sx || __builtin_rintf(sy) != sy) return UH_ERR_GRID;
-  return 0;
+  const float fr = __builtin_amdgcn_fractf(v.x * 0x1p30f) + __builtin_amdgcn_fractf(v.y * 0x1p30f);
+  return fr == 0.0f ? 0 : UH_ERR_GRID;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -131,169 +130,263 @@ __global__ void init_kernel(int32_t S, RunArgs A) {
 }
 
 // ---------------------------------------------------------------- tiles
+// Workgroup barrier that orders LDS only: unlike __syncthreads it does not
+// wait for outstanding global loads, so a prefetch stays in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Wave-level inclusive max scans (prefix: lanes below; suffix: lanes above).
+__device__ __forceinline__ float wave_prefix_max(float v) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    const float y = __shfl_up(v, o, 64);
+    if (lane >= o) v = fmaxf(v, y);
+  }
+  return v;
+}
+__device__ __forceinline__ float wave_suffix_max(float v) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    const float y = __shfl_down(v, o, 64);
+    if (lane + o < 64) v = fmaxf(v, y);
+  }
+  return v;
+}
+
+// Adds a wave's orientation counters to stats[set].
+__device__ __forceinline__ void flush_wave_stats(const RunArgs &A, int set, OrientCount &oc) {
+  if (!A.stats) return;
+  const uint32_t e = wave_sum(oc.evals), f = wave_sum(oc.fallbacks);
+  if ((threadIdx.x & 63) == 0 && A.stats && e) {
+    atomicAdd((unsigned long long *)&A.stats[set].orient_evals, (unsigned long long)e);
+    atomicAdd((unsigned long long *)&A.stats[set].fallbacks, (unsigned long long)f);
+  }
+  oc.evals = oc.fallbacks = 0;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Tile kernel: one wave (one workgroup of 64 lanes) per tile of up to
+// T = 64 * K points of one set; no workgroup barrier anywhere.
+//  1. coalesced 16-byte loads (two points per lane per load), the data
+//     contract's range and grid checks, then the points go to per-lane
+//     strips of K consecutive points in LDS (stride K + 2: 16-byte aligned)
+//     and each lane reads its strip back into registers;
+//  2. strip pass 1: maximum y of each strip, x non-decreasing check (the
+//     previous strip's last point comes from the neighbouring lane); wave
+//     prefix and suffix maxima over the strips;
+//  3. strip pass 2: exact elimination, then the strip hood.  A point r is
+//     dropped when some earlier point of the tile is at least as high and
+//     some later point is strictly higher: r then lies below the segment
+//     joining the first earlier maximum and the last later maximum (both of
+//     which survive), or directly below a point at its x, so it is no corner
+//     of the tile's hood (nor is any identical copy of it that survives only
+//     because it comes later).  The survivors go through a serial monotone
+//     chain whose stack lives in the strip's LDS slot (the serial strip
+//     hoods of the paper's work-optimal variant);
+//  4. six rounds of Wagener merges (match-and-merge on adjacent hoods,
+//     block size K * 2^j -> K * 2^(j+1)), the 2^(j+1) lanes of each merge
+//     acting as the paper's d1 x d2 thread block;
+//  5. the tile's hood goes to the workspace, or to the output for a
+//     one-tile set.
 template <int K>
-__global__ __launch_bounds__(BLOCK) void tile_kernel(RunArgs A,
-                                                     const TileItem *items,
-                                                     int32_t *cnt_out) {
-  constexpr int S = K + 1;  // LDS strip stride (odd: spreads banks)
-  __shared__ float2 sxy[BLOCK * S];
-  __shared__ uint16_t sid[BLOCK * S];
-  __shared__ int scnt[BLOCK];
-  __shared__ int2 sres[BLOCK / 2];
-  __shared__ int serr;
-  __shared__ unsigned long long sstat[2];
+__global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
+                                                  int32_t *cnt_out) {
+  constexpr int S = K + 2;
+  constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
+  __shared__ __attribute__((aligned(16))) float2 sxy[64 * S];
+  __shared__ uint16_t sid[64 * S];
+  __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
 
   const TileItem it = items[blockIdx.x];
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
   const int64_t sstart = A.set_start[it.set];
-  if (tid == 0) {
-    serr = 0;
-    sstat[0] = sstat[1] = 0;
-  }
-
-  // ---- load: coalesced reads, scattered into per-lane strips in LDS
-  int err = 0;
   const float2 *src = A.pts + it.start;
-#pragma unroll 4
-  for (int r = 0; r < K; ++r) {
-    const int e = tid + r * BLOCK;
-    if (e < it.len) {
-      const float2 v = src[e];
-      if (validate) err = min(err, check_point(v));
-      sxy[(e / K) * S + (e % K)] = v;
+
+  // ---- 1. load
+  float4 v[NV];
+  int err = 0;
+  float prev_tile_x = -1.0f;  // below every valid x
+  if (validate && lane == 0 && it.start > sstart) prev_tile_x = A.pts[it.start - 1].x;
+  // Witnesses from the neighbouring tiles of the same set: the maximum y of
+  // up to 16 points just before the tile and of up to 16 just after it
+  // (lanes 0-15 fetch them, two points each).  Any earlier / later point of
+  // the set may serve the elimination test below, and these let the first
+  // and last strips drop their points too.
+  float nb_before = -2.0f, nb_after = -2.0f;
+  {
+    const int64_t send = A.set_start[it.set + 1];
+    float wy = -2.0f;
+    if (lane < 8) {
+      const int64_t e = it.start - 16 + 2 * lane;
+      if (e >= sstart) wy = fmaxf(A.pts[e].y, A.pts[e + 1].y);
+    } else if (lane < 16) {
+      const int64_t e = it.start + it.len + 2 * (lane - 8);
+      if (e + 1 < send) wy = fmaxf(A.pts[e].y, A.pts[e + 1].y);
+      else if (e < send) wy = A.pts[e].y;
+    }
+    for (int o = 4; o > 0; o >>= 1) wy = fmaxf(wy, __shfl_xor(wy, o, 64));
+    nb_before = __shfl(wy, 0, 64);
+    nb_after = __shfl(wy, 8, 64);
+  }
+  if (it.len == 64 * K && (((uintptr_t)src) & 15u) == 0) {
+    // full, 16-byte aligned tile (the common case): no per-element tests
+    const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
+#pragma unroll
+    for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      if (validate)
+        err = min(err, min(check_point(make_float2(v[r].x, v[r].y)),
+                           check_point(make_float2(v[r].z, v[r].w))));
+      float4 *d = reinterpret_cast<float4 *>(
+          __builtin_assume_aligned(sxy + (e / K) * S + (e % K), 16));
+      *d = v[r];
+    }
+  } else {
+    const bool al = (((uintptr_t)src) & 15u) == 0;
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      if (e + 1 < it.len) {
+        if (al) {
+          v[r] = *reinterpret_cast<const float4 *>(src + e);
+        } else {
+          const float2 a = src[e], b = src[e + 1];
+          v[r] = make_float4(a.x, a.y, b.x, b.y);
+        }
+      } else if (e < it.len) {
+        const float2 a = src[e];
+        v[r] = make_float4(a.x, a.y, 0.f, 0.f);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      if (e < it.len) {
+        float2 *d = sxy + (e / K) * S + (e % K);
+        if (validate) {
+          err = min(err, check_point(make_float2(v[r].x, v[r].y)));
+          if (e + 1 < it.len) err = min(err, check_point(make_float2(v[r].z, v[r].w)));
+        }
+        if (e + 1 < it.len)
+          *reinterpret_cast<float4 *>(d) = v[r];
+        else
+          *d = make_float2(v[r].x, v[r].y);
+      }
     }
   }
-  __syncthreads();
-  const int my_len = min(max(it.len - tid * K, 0), K);
-  float prevx = -1.0f;  // below every valid x
-  if (validate && my_len > 0) {
-    if (tid > 0)
-      prevx = sxy[(tid - 1) * S + (K - 1)].x;
-    else if (it.start > sstart)
-      prevx = A.pts[it.start - 1].x;
+  wave_sync();
+  const int my_len = min(max(it.len - lane * K, 0), K);
+  float2 *st = sxy + lane * S;
+  uint16_t *sl = sid + lane * S;
+  float2 p[K];
+#pragma unroll
+  for (int k = 0; k < K / 2; ++k) {
+    const float4 q = *reinterpret_cast<const float4 *>(st + 2 * k);
+    p[2 * k] = make_float2(q.x, q.y);
+    p[2 * k + 1] = make_float2(q.z, q.w);
   }
-  __syncthreads();
 
-  // ---- strip hood: monotone chain over this lane's K points, in place
+  // ---- 2. strip pass 1
   OrientCount oc;
-  int cnt = 0;
-  if (my_len > 0) {
-    float2 *st = sxy + tid * S;
-    uint16_t *sl = sid + tid * S;
-    float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
-    int i = 0;
-    float2 r = st[0];
-    if (validate && r.x < prevx) err = min(err, UH_ERR_UNSORTED);
-    float px = r.x;
-    while (i < my_len) {
-      bool pop = false, skip = false;
-      if (cnt >= 1 && r.x == t1.x) {
-        if (r.y > t1.y)
-          pop = true;  // r hides the top (same x, higher)
-        else
-          skip = true;  // the top hides r (ties keep the lower index)
-      } else if (cnt >= 2) {
-        pop = orient_sign(t2, t1, r, oc, fe) >= 0;  // top on/below t2 -> r
+  float ymax = -2.0f;  // below every valid y
+  {
+    float px = __shfl_up(p[K - 1].x, 1, 64);  // last point of the previous strip
+    if (lane == 0) px = prev_tile_x;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (i < my_len) {
+        ymax = fmaxf(ymax, p[i].y);
+        if (validate && p[i].x < px) err = min(err, UH_ERR_UNSORTED);
+        px = p[i].x;
       }
-      if (pop) {
-        --cnt;
+    }
+  }
+  const float incp = wave_prefix_max(ymax), incs = wave_suffix_max(ymax);
+  float exp_pre = __shfl_up(incp, 1, 64), exp_suf = __shfl_down(incs, 1, 64);
+  if (lane == 0) exp_pre = -2.0f;
+  if (lane == 63) exp_suf = -2.0f;
+  exp_pre = fmaxf(exp_pre, nb_before);
+  exp_suf = fmaxf(exp_suf, nb_after);
+
+  // ---- 3. strip pass 2: elimination (from registers), then the serial
+  //         strip hood over the survivors (re-read from LDS; the stack
+  //         overwrites the slot from its start, never past a survivor
+  //         still to be read)
+  uint32_t keep = 0;
+  {
+    float bm = exp_pre;  // max y over earlier points of the tile
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (i < my_len && (p[i].y > bm || p[i].y >= exp_suf)) keep |= 1u << i;
+      bm = fmaxf(bm, p[i].y);
+    }
+  }
+  int cnt = 0;
+  {
+    float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
+    while (keep) {
+      const int i = __builtin_ctz(keep);
+      keep &= keep - 1;
+      const float2 r = st[i];
+      if (cnt >= 1 && r.x == t1.x) {
+        if (r.y <= t1.y) continue;  // the top hides r (ties: lower index)
+        --cnt;                      // r hides the top
         t1 = t2;
         if (cnt >= 2) t2 = st[cnt - 2];
-      } else {
-        if (!skip) {
-          st[cnt] = r;
-          sl[cnt] = (uint16_t)(tid * K + i);
-          t2 = t1;
-          t1 = r;
-          ++cnt;
-        }
-        ++i;
-        if (i < my_len) {
-          r = st[i];
-          if (validate && r.x < px) err = min(err, UH_ERR_UNSORTED);
-          px = r.x;
-        }
       }
+      while (cnt >= 2 && orient_sign(t2, t1, r, oc, fe) >= 0) {
+        --cnt;  // the top is on or below t2 -> r
+        t1 = t2;
+        if (cnt >= 2) t2 = st[cnt - 2];
+      }
+      st[cnt] = r;
+      sl[cnt] = (uint16_t)(lane * K + i);
+      t2 = t1;
+      t1 = r;
+      ++cnt;
     }
   }
-  scnt[tid] = cnt;
-  __syncthreads();
+  // Leaves of the merge tree: the non-empty strip hoods, in order.  Nothing
+  // between two consecutive leaves survived, so merging neighbouring leaves
+  // is merging hoods of x-adjacent point sets.
+  const uint64_t ne = __ballot(cnt > 0);
+  const int nleaf = __builtin_popcountll(ne);
+  if (cnt > 0) sblk[__builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(lane * S, cnt);
+  wave_sync();
 
-  // ---- rounds of Wagener merges: block size K * 2^j -> K * 2^(j+1)
-#pragma unroll 1
-  for (int j = 0; j < LOG2_BLOCK; ++j) {
-    const int G = 2 << j;  // lanes per merge
-    const int m = tid >> (j + 1);
-    const int t = tid & (G - 1);
-    const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
-    float2 *P = sxy + lp * S;
-    float2 *Q = sxy + lq * S;
-    uint16_t *Pid = sid + lp * S;
-    const uint16_t *Qid = sid + lq * S;
-    int hp = scnt[lp];
-    const int hq = scnt[lq];
-    int qs = 0;
-    if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
-    const int hqe = hq - qs;
-    int a = hp - 1, b = 0;
-    const int L = G < 64 ? G : 64;
-    if (hp > 0 && hqe > 0 && t < L)
-      bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t,
-                                    a, b, oc, fe);
-    if (G > 64) {  // the search ran in the group's first wave: share it
-      if (t == 0) sres[m] = make_int2(a, b);
-      __syncthreads();
-      const int2 rr = sres[m];
-      a = rr.x;
-      b = rr.y;
-    }
-    // mam6, compacted: P[0..a] stays, Q[b..] moves to P[a+1..]
-    const int nsurv = hqe - b;
-    constexpr int PER = K / 2;  // Q holds <= K*2^j corners, G = 2^(j+1) lanes
-    float2 v[PER];
-    uint16_t vi[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = t + k * G;
-      if (e < nsurv) {
-        v[k] = Q[qs + b + e];
-        vi[k] = Qid[qs + b + e];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = t + k * G;
-      if (e < nsurv) {
-        P[a + 1 + e] = v[k];
-        Pid[a + 1 + e] = vi[k];
-      }
-    }
-    if (t == 0) scnt[lp] = a + 1 + nsurv;
-    __syncthreads();
-  }
+  // ---- 4. rounds of Wagener merges over the leaves
+  wave_rounds(sxy, sid, sblk, nleaf, oc, fe);
 
-  // ---- output
-  if (err) atomicMin(&serr, err);
-  flush_stats(A, it.set, oc, sstat);  // contains a barrier
-  const int hc = scnt[0];
+  // ---- 5. output
+  err = wave_min(err);
+  const int hb = nleaf ? sblk[0].x : 0, hc = nleaf ? sblk[0].y : 0;
   const int rel0 = (int)(it.start - sstart);
   if (it.final_) {
     int32_t *dst = A.out_idx + sstart;
-    for (int k = tid; k < hc; k += BLOCK) dst[k] = rel0 + (int)sid[k];
-    if (tid == 0) A.out_counts[it.set] = serr ? serr : hc;
+    for (int k = lane; k < hc; k += 64) dst[k] = rel0 + (int)sid[hb + k];
+    if (lane == 0) A.out_counts[it.set] = err ? err : hc;
   } else {
-    for (int k = tid; k < hc; k += BLOCK) {
-      A.ws_xy[it.start + k] = sxy[k];
-      A.ws_idx[it.start + k] = rel0 + (int)sid[k];
+    for (int k = lane; k < hc; k += 64) {
+      A.ws_xy[it.start + k] = sxy[hb + k];
+      A.ws_idx[it.start + k] = rel0 + (int)sid[hb + k];
     }
-    if (tid == 0) {
+    if (lane == 0) {
       cnt_out[blockIdx.x] = hc;
-      if (serr) atomicMin(&A.set_status[it.set], serr);
+      if (err) atomicMin(&A.set_status[it.set], err);
     }
   }
+  flush_wave_stats(A, it.set, oc);
 }
 
 // ---------------------------------------------------------------- merges
@@ -316,193 +409,209 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &tota
   return before + x - v;
 }
 
+// One workgroup merges the hoods of up to F = 256 consecutive blocks of the
+// previous level of one set (log2 F more rounds).  When their corners fit
+// in LDS: gather them back to back, six rounds inside each wave (64
+// children -> 1), then wave 0 merges the four wave hoods.  Otherwise the
+// same rounds run in place in the workspace (global memory), each merge by
+// a group of lanes with workgroup barriers between the reads and writes of
+// the compaction.
 __global__ __launch_bounds__(BLOCK) void merge_kernel(
     RunArgs A, const MergeItem *items, const int64_t *child_off,
     const int32_t *child_cnt, int32_t *cnt_out) {
-  __shared__ float2 bxy[2][VMAX];
-  __shared__ int32_t bid[2][VMAX];
-  __shared__ int choff[BLOCK + 1];
+  __shared__ float2 bxy[VMAX];
+  __shared__ int32_t bid[VMAX];
   __shared__ int bcnt[BLOCK];
+  __shared__ int2 sblk[BLOCK];  // LDS path: (base, count) per child block
   __shared__ int2 sres[BLOCK / 2];
   __shared__ int swave[BLOCK / 64];
   __shared__ int smax;
-  __shared__ unsigned long long sstat[2];
 
   const MergeItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const int nch = it.nch;
-  if (tid == 0) sstat[0] = sstat[1] = 0;
 
   const int c = tid < nch ? child_cnt[it.child0 + tid] : 0;
   int V;
   const int o = block_exclusive_scan(c, swave, V);
-  choff[tid] = o;
   bcnt[tid] = c;
-  if (tid == 0) choff[BLOCK] = V;
   int npow = 1;
   while (npow < nch) npow <<= 1;
   OrientCount oc;
   __syncthreads();
 
-  int hc;                  // final corner count
-  const float2 *res_xy;    // final corners (LDS or workspace)
-  const int32_t *res_id;
   if (V <= VMAX) {
-    // ---- gather the children's corners into LDS, back to back
-    for (int v = tid; v < V; v += BLOCK) {
-      int lo = 0, hi = nch - 1;  // last k with choff[k] <= v
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (choff[mid] <= v)
-          lo = mid;
-        else
-          hi = mid - 1;
+    // ---- gather: thread k copies child k's corners (independent loads)
+    if (tid < nch) {
+      const int64_t g = child_off[it.child0 + tid];
+      for (int e = 0; e < c; ++e) {
+        bxy[o + e] = A.ws_xy[g + e];
+        bid[o + e] = A.ws_idx[g + e];
       }
-      const int64_t g = child_off[it.child0 + lo] + (v - choff[lo]);
-      bxy[0][v] = A.ws_xy[g];
-      bid[0][v] = A.ws_idx[g];
     }
     __syncthreads();
-    int cur = 0;
-#pragma unroll 1
-    for (int j = 0; (1 << j) < nch; ++j) {
-      const int M = npow >> (j + 1);  // merges at this round
-      const int G = BLOCK / M;
-      const int m = tid / G, t = tid % G;
-      const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
-      const float2 *sxy = bxy[cur];
-      const int32_t *sid = bid[cur];
-      float2 *dxy = bxy[cur ^ 1];
-      int32_t *did = bid[cur ^ 1];
-      int a = -1, b = 0, hp = 0, hqe = 0, qs = 0, op = 0, oq = 0;
-      if (lp < nch) {
-        op = choff[lp];
-        hp = bcnt[lp];
-        int hq = 0;
-        if (lq < nch) {
-          oq = choff[lq];
-          hq = bcnt[lq];
-        }
-        if (hp > 0 && hq > 0) junction_rule(sxy[op + hp - 1], sxy[oq], hp, qs);
-        hqe = hq - qs;
-        a = hp - 1;
-        const int L = G < 64 ? G : 64;
-        if (hp > 0 && hqe > 0 && t < L)
-          bridge_search<const float2 *>(sxy + op, hp, sxy + oq + qs, hqe, L, t,
-                                        (tid & 63) - t, a, b, oc, fe);
-      }
-      if (G > 64) {
-        if (t == 0) sres[m] = make_int2(a, b);
-        __syncthreads();
-        const int2 rr = sres[m];
-        a = rr.x;
-        b = rr.y;
-      }
-      if (lp < nch) {
-        const int nsurv = hqe - b;
-        for (int e = t; e <= a; e += G) {
-          dxy[op + e] = sxy[op + e];
-          did[op + e] = sid[op + e];
-        }
-        for (int e = t; e < nsurv; e += G) {
-          dxy[op + a + 1 + e] = sxy[oq + qs + b + e];
-          did[op + a + 1 + e] = sid[oq + qs + b + e];
-        }
-        if (t == 0) bcnt[lp] = a + 1 + nsurv;
-      }
+    // Exact elimination over the gathered corners (a sorted point list): a
+    // corner is dropped when an earlier one is at least as high and a later
+    // one strictly higher (the tile kernel's rule; witnesses are earlier
+    // corners and later children's maxima).  Each thread filters its child
+    // in place; what is left of a strictly concave chain is still one, so
+    // every child stays a hood.
+    {
+      float cmax = -2.0f;
+      for (int e = 0; e < c; ++e) cmax = fmaxf(cmax, bxy[o + e].y);
+      const float incp = wave_prefix_max(cmax), incs = wave_suffix_max(cmax);
+      __shared__ float swp[BLOCK / 64], sws[BLOCK / 64];
+      if (lane == 63) swp[w] = incp;
+      if (lane == 0) sws[w] = incs;
+      float pre = __shfl_up(incp, 1, 64), suf = __shfl_down(incs, 1, 64);
+      if (lane == 0) pre = -2.0f;
+      if (lane == 63) suf = -2.0f;
       __syncthreads();
-      cur ^= 1;
+      for (int k = 0; k < BLOCK / 64; ++k) {
+        if (k < w) pre = fmaxf(pre, swp[k]);
+        if (k > w) suf = fmaxf(suf, sws[k]);
+      }
+      int kept = 0;
+      for (int e = 0; e < c; ++e) {
+        const float2 q = bxy[o + e];
+        const bool keep = q.y > pre || q.y >= suf;
+        pre = fmaxf(pre, q.y);
+        if (keep) {
+          const int32_t qi = bid[o + e];
+          bxy[o + kept] = q;
+          bid[o + kept] = qi;
+          ++kept;
+        }
+      }
+      // leaves: the non-empty children, in order, 64 per wave
+      const uint64_t ne = __ballot(kept > 0);
+      if (kept > 0)
+        sblk[(w << 6) + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
+      if (lane == 0) swave[w] = __builtin_popcountll(ne);
     }
-    hc = bcnt[0];
-    res_xy = bxy[cur];
-    res_id = bid[cur];
-  } else {
-    // ---- too large for LDS: the same rounds in place in the workspace
-#pragma unroll 1
-    for (int j = 0; (1 << j) < nch; ++j) {
-      const int M = npow >> (j + 1);
-      const int G = BLOCK / M;
-      const int m = tid / G, t = tid % G;
-      const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
-      int a = -1, b = 0, hp = 0, hqe = 0, qs = 0;
-      float2 *P = nullptr, *Q = nullptr;
-      int32_t *Pid = nullptr, *Qid = nullptr;
-      if (tid == 0) smax = 0;
-      if (lp < nch && lq < nch) {
-        const int64_t op = child_off[it.child0 + lp], oq = child_off[it.child0 + lq];
-        P = A.ws_xy + op;
-        Q = A.ws_xy + oq;
-        Pid = A.ws_idx + op;
-        Qid = A.ws_idx + oq;
-        hp = bcnt[lp];
-        const int hq = bcnt[lq];
-        if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
-        hqe = hq - qs;
-        a = hp - 1;
-        const int L = G < 64 ? G : 64;
-        if (hp > 0 && hqe > 0 && t < L)
-          bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t,
-                                        a, b, oc, fe);
-      }
-      __syncthreads();  // smax cleared, and searches done reading
-      if (G > 64) {
-        if (t == 0) sres[m] = make_int2(a, b);
-        __syncthreads();
-        const int2 rr = sres[m];
-        a = rr.x;
-        b = rr.y;
-      }
-      const bool active = lp < nch && lq < nch;
-      const int nsurv = active ? hqe - b : 0;
-      const int chunks = (nsurv + G - 1) / G;
-      if (t == 0 && active) atomicMax(&smax, chunks);
-      __syncthreads();
-      const int maxchunks = smax;
-      // left shift Q[b..] to P[a+1..]: destination never passes the source,
-      // so reading chunk c before anyone writes it keeps every value intact
-      for (int ch = 0; ch < maxchunks; ++ch) {
-        const int e = ch * G + t;
-        float2 v = make_float2(0.f, 0.f);
-        int32_t vi = 0;
-        const bool mine = e < nsurv;
-        if (mine) {
-          v = Q[qs + b + e];
-          vi = Qid[qs + b + e];
+    __syncthreads();
+    wave_rounds(bxy, bid, sblk + (w << 6), swave[w], oc, fe);
+    __syncthreads();
+    if (w == 0) {
+      // the wave hoods (one per wave that had leaves), left to right
+      int nb0 = 0, nc0 = 0;
+      bool have = false;
+      for (int k = 0; k < BLOCK / 64; ++k) {
+        if (swave[k] == 0) continue;
+        const int2 Q = sblk[k << 6];
+        if (!have) {
+          nb0 = Q.x;
+          nc0 = Q.y;
+          have = true;
+          continue;
         }
-        __syncthreads();
-        if (mine) {
-          P[a + 1 + e] = v;
-          Pid[a + 1 + e] = vi;
-        }
-        __syncthreads();
+        int nb, nc;
+        merge_blocks(bxy, bid, nb0, nc0, Q.x, Q.y, 6, lane, 0, nb, nc, oc, fe);
+        wave_sync();
+        nb0 = nb;
+        nc0 = nc;
       }
-      if (t == 0 && active) bcnt[lp] = a + 1 + nsurv;
-      __syncthreads();
+      if (lane == 0) sblk[0] = make_int2(nb0, nc0);
+      wave_sync();
+      const int hb = sblk[0].x, hc = sblk[0].y;
+      if (it.final_) {
+        int32_t *dst = A.out_idx + A.set_start[it.set];
+        for (int k = lane; k < hc; k += 64) dst[k] = bid[hb + k];
+        if (lane == 0) {
+          const int st = A.set_status[it.set];
+          A.out_counts[it.set] = st ? st : hc;
+        }
+      } else {
+        for (int k = lane; k < hc; k += 64) {
+          A.ws_xy[it.off + k] = bxy[hb + k];
+          A.ws_idx[it.off + k] = bid[hb + k];
+        }
+        if (lane == 0) cnt_out[blockIdx.x] = hc;
+      }
     }
-    hc = bcnt[0];
-    res_xy = A.ws_xy + it.off;
-    res_id = A.ws_idx + it.off;
+    flush_wave_stats(A, it.set, oc);
+    return;
   }
 
-  flush_stats(A, it.set, oc, sstat);  // contains a barrier
+  // ---- too large for LDS: the same rounds in place in the workspace
+#pragma unroll 1
+  for (int j = 0; (1 << j) < nch; ++j) {
+    const int M = npow >> (j + 1);
+    const int G = BLOCK / M;
+    const int m = tid / G, t = tid % G;
+    const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
+    int a = -1, b = 0, hp = 0, hqe = 0, qs = 0;
+    float2 *P = nullptr, *Q = nullptr;
+    int32_t *Pid = nullptr, *Qid = nullptr;
+    if (tid == 0) smax = 0;
+    if (lp < nch && lq < nch) {
+      const int64_t op = child_off[it.child0 + lp], oq = child_off[it.child0 + lq];
+      P = A.ws_xy + op;
+      Q = A.ws_xy + oq;
+      Pid = A.ws_idx + op;
+      Qid = A.ws_idx + oq;
+      hp = bcnt[lp];
+      const int hq = bcnt[lq];
+      if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
+      hqe = hq - qs;
+      a = hp - 1;
+      const int L = G < 64 ? G : 64;
+      if (hp > 0 && hqe > 0 && t < L)
+        bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t, a, b, oc,
+                                      fe);
+    }
+    __syncthreads();  // smax cleared, and searches done reading
+    if (G > 64) {
+      if (t == 0) sres[m] = make_int2(a, b);
+      __syncthreads();
+      const int2 rr = sres[m];
+      a = rr.x;
+      b = rr.y;
+    }
+    const bool active = lp < nch && lq < nch;
+    const int nsurv = active ? hqe - b : 0;
+    const int chunks = (nsurv + G - 1) / G;
+    if (t == 0 && active) atomicMax(&smax, chunks);
+    __syncthreads();
+    const int maxchunks = smax;
+    // left shift Q[b..] to P[a+1..]: destination never passes the source,
+    // so reading chunk c before anyone writes it keeps every value intact
+    for (int ch = 0; ch < maxchunks; ++ch) {
+      const int e = ch * G + t;
+      float2 v = make_float2(0.f, 0.f);
+      int32_t vi = 0;
+      const bool mine = e < nsurv;
+      if (mine) {
+        v = Q[qs + b + e];
+        vi = Qid[qs + b + e];
+      }
+      __syncthreads();
+      if (mine) {
+        P[a + 1 + e] = v;
+        Pid[a + 1 + e] = vi;
+      }
+      __syncthreads();
+    }
+    if (t == 0 && active) bcnt[lp] = a + 1 + nsurv;
+    __syncthreads();
+  }
+  const int hc = bcnt[0];
+  const float2 *res_xy = A.ws_xy + it.off;
+  const int32_t *res_id = A.ws_idx + it.off;
   if (it.final_) {
-    const int64_t sstart = A.set_start[it.set];
-    int32_t *dst = A.out_idx + sstart;
+    int32_t *dst = A.out_idx + A.set_start[it.set];
     for (int k = tid; k < hc; k += BLOCK) dst[k] = res_id[k];
     if (tid == 0) {
       const int st = A.set_status[it.set];
       A.out_counts[it.set] = st ? st : hc;
     }
   } else {
-    if (V <= VMAX) {
-      for (int k = tid; k < hc; k += BLOCK) {
-        A.ws_xy[it.off + k] = res_xy[k];
-        A.ws_idx[it.off + k] = res_id[k];
-      }
-    }
+    (void)res_xy;
     if (tid == 0) cnt_out[blockIdx.x] = hc;
   }
+  flush_wave_stats(A, it.set, oc);
 }
 
 // ---------------------------------------------------------------- probes
@@ -597,7 +706,7 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
     hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, stream, p->S, A);
   }
   if (p->ntiles > 0) {
-    const dim3 grid(p->ntiles), blk(BLOCK);
+    const dim3 grid(p->ntiles), blk(64);
     if (p->probe_before && hipEventRecord(p->probe_before, stream) != hipSuccess)
       return UH_ERR_HIP;
     switch (p->K) {
@@ -665,7 +774,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   p->S = num_sets;
   p->N = set_offsets[num_sets];
   p->K = K;
-  p->T = BLOCK * K;
+  p->T = 64 * K;
   p->F = F;
   p->flags = flags;
 

@@ -63,6 +63,9 @@ def _check_pair(P, Q):
     assert tang[a] == b
     # merge = hood of the union
     assert B.merge(P, Q) == _hood(P + Q)
+    # the corner-wise survival test picks exactly P[0..a] and Q[b..]
+    kp, kq = B.survivors(P, Q)
+    assert kp == list(range(a + 1)) and kq == list(range(b, len(Q))), (P, Q)
 
 
 def test_exhaustive_small_hoods():

@@ -127,7 +127,7 @@ TILE = 4096
 @pytest.mark.parametrize("n", [TILE - 1, TILE, TILE + 1, 2 * TILE - 1, 2 * TILE + 1,
                                7 * TILE + 3, 256 * TILE + 5])
 def test_sizes_around_tiles(n):
-    assert_parity(synth.uniform(n, 20, seed=n))
+    assert_parity(synth.uniform(n, 22, seed=n))
     assert_parity(synth.arc(min(n, 1 << 20), 20, 4, seed=n + 1))
 
 
@@ -150,7 +150,7 @@ def test_concave_all_corners_global_path():
     # every point is a corner: tile hoods are full, merges exceed LDS
     xy = concave_chain()
     n = len(xy)
-    assert n > 3 * TILE
+    assert n > 2 * TILE
     ref = oracle.upper_hull(xy)
     assert np.array_equal(ref, np.arange(n))
     c, idx = gpu_hull(xy)
