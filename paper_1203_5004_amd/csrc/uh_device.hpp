@@ -365,6 +365,38 @@ __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
   }
 }
 
+// Serial monotone chain (upper half) over n points stored at xy / id in
+// x order, in place: afterwards the first `return value` entries are the
+// strict upper hood of the n points (the paper's serial strip hood).  Equal
+// x: only the highest point can stay, ties keep the earlier (lower index)
+// one.  Works on LDS or global memory (one thread owns the range).
+template <class PT, class IT>
+__device__ __forceinline__ int chain_inplace(PT xy, IT id, int n, OrientCount &oc, bool fe) {
+  int cnt = 0;
+  float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
+  for (int i = 0; i < n; ++i) {
+    const float2 r = xy[i];
+    if (cnt >= 1 && r.x == t1.x) {
+      if (r.y <= t1.y) continue;  // the top hides r
+      --cnt;                      // r hides the top
+      t1 = t2;
+      if (cnt >= 2) t2 = xy[cnt - 2];
+    }
+    while (cnt >= 2 && orient_sign(t2, t1, r, oc, fe) >= 0) {
+      --cnt;  // the top is on or below t2 -> r
+      t1 = t2;
+      if (cnt >= 2) t2 = xy[cnt - 2];
+    }
+    const auto ri = id[i];
+    xy[cnt] = r;
+    id[cnt] = ri;
+    t2 = t1;
+    t1 = r;
+    ++cnt;
+  }
+  return cnt;
+}
+
 // Rounds of Wagener merges over nleaf <= 64 leaf hoods, run by one whole
 // wave: blk[0..nleaf) hold (base, count) of consecutive, x-adjacent,
 // non-empty hoods in the LDS arrays xy / id.  Round j joins blocks of 2^j

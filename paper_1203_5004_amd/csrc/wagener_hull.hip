@@ -44,6 +44,10 @@ namespace uh {
 
 constexpr int BLOCK = 256;       // threads per workgroup (4 waves)
 constexpr int VMAX = 8192;       // corners a merge workgroup keeps in LDS
+// Bit 31 of a tile's output count: the tile wrote its surviving points (a
+// sorted point list, not yet a hood); the merge kernel makes it a hood.
+constexpr uint32_t POINTS_FLAG = 0x80000000u;
+constexpr int TILE_LIST_MAX = 64;  // most survivors a tile hands on as a list
 
 struct TileItem {    // one tile of the tile pass
   int64_t start;     // first point (absolute)
@@ -242,16 +246,26 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
 #pragma unroll
     for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
+    bool range_ok = true;
+    float frac = 0.0f;  // sum of fractions of coordinate * 2^30: 0 iff all on grid
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
-      if (validate)
-        err = min(err, min(check_point(make_float2(v[r].x, v[r].y)),
-                           check_point(make_float2(v[r].z, v[r].w))));
+      if (validate) {
+        range_ok = range_ok && __builtin_fabsf(v[r].x - 0.5f) <= 0.5f &&
+                   __builtin_fabsf(v[r].z - 0.5f) <= 0.5f && __builtin_fabsf(v[r].y) <= 1.0f &&
+                   __builtin_fabsf(v[r].w) <= 1.0f;
+        frac += (__builtin_amdgcn_fractf(v[r].x * 0x1p30f) +
+                 __builtin_amdgcn_fractf(v[r].y * 0x1p30f)) +
+                (__builtin_amdgcn_fractf(v[r].z * 0x1p30f) +
+                 __builtin_amdgcn_fractf(v[r].w * 0x1p30f));
+      }
       float4 *d = reinterpret_cast<float4 *>(
           __builtin_assume_aligned(sxy + (e / K) * S + (e % K), 16));
       *d = v[r];
     }
+    if (!range_ok) err = UH_ERR_RANGE;
+    else if (frac != 0.0f) err = UH_ERR_GRID;
   } else {
     const bool al = (((uintptr_t)src) & 15u) == 0;
 #pragma unroll
@@ -319,10 +333,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   exp_pre = fmaxf(exp_pre, nb_before);
   exp_suf = fmaxf(exp_suf, nb_after);
 
-  // ---- 3. strip pass 2: elimination (from registers), then the serial
-  //         strip hood over the survivors (re-read from LDS; the stack
-  //         overwrites the slot from its start, never past a survivor
-  //         still to be read)
+  // ---- 3. strip pass 2: elimination (from registers)
   uint32_t keep = 0;
   {
     float bm = exp_pre;  // max y over earlier points of the tile
@@ -332,8 +343,42 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       bm = fmaxf(bm, p[i].y);
     }
   }
-  int cnt = 0;
-  {
+  // Survivors of the whole wave, counted and ranked by a wave prefix sum.
+  const int nk = __builtin_popcount(keep);
+  int koff = nk;  // inclusive prefix sum of nk over the lanes
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(koff, o, 64);
+    if (lane >= o) koff += y;
+  }
+  const int nsurv = __shfl(koff, 63, 64);
+  koff -= nk;
+  int nleaf;
+  if (!it.final_ && nsurv <= TILE_LIST_MAX) {
+    // Few survivors: hand them on, in order, as a point list; the merge
+    // kernel turns them into a hood after eliminating across many tiles.
+    err = wave_min(err);
+    const int rel0 = (int)(it.start - sstart);
+    int r = koff;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if ((keep >> i) & 1u) {
+        A.ws_xy[it.start + r] = p[i];
+        A.ws_idx[it.start + r] = rel0 + lane * K + i;
+        ++r;
+      }
+    }
+    if (lane == 0) {
+      cnt_out[blockIdx.x] = (int)((uint32_t)nsurv | POINTS_FLAG);
+      if (err) atomicMin(&A.set_status[it.set], err);
+    }
+    flush_wave_stats(A, it.set, oc);
+    return;
+  } else {
+    // Many survivors: the serial strip hood over each strip's survivors
+    // (re-read from LDS; the stack overwrites the slot from its start,
+    // never past a survivor still to be read), then the non-empty strip
+    // hoods are the leaves.
+    int cnt = 0;
     float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
     while (keep) {
       const int i = __builtin_ctz(keep);
@@ -356,14 +401,14 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       t1 = r;
       ++cnt;
     }
+    // Leaves of the merge tree: the non-empty strip hoods, in order.
+    // Nothing between two consecutive leaves survived, so merging
+    // neighbouring leaves is merging hoods of x-adjacent point sets.
+    const uint64_t ne = __ballot(cnt > 0);
+    nleaf = __builtin_popcountll(ne);
+    if (cnt > 0) sblk[__builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(lane * S, cnt);
+    wave_sync();
   }
-  // Leaves of the merge tree: the non-empty strip hoods, in order.  Nothing
-  // between two consecutive leaves survived, so merging neighbouring leaves
-  // is merging hoods of x-adjacent point sets.
-  const uint64_t ne = __ballot(cnt > 0);
-  const int nleaf = __builtin_popcountll(ne);
-  if (cnt > 0) sblk[__builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(lane * S, cnt);
-  wave_sync();
 
   // ---- 4. rounds of Wagener merges over the leaves
   wave_rounds(sxy, sid, sblk, nleaf, oc, fe);
@@ -433,7 +478,10 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const int nch = it.nch;
 
-  const int c = tid < nch ? child_cnt[it.child0 + tid] : 0;
+  // a child is a hood, or (POINTS_FLAG) a tile's sorted surviving points
+  const uint32_t craw = tid < nch ? (uint32_t)child_cnt[it.child0 + tid] : 0u;
+  const bool pts = (craw & POINTS_FLAG) != 0;
+  const int c = (int)(craw & ~POINTS_FLAG);
   int V;
   const int o = block_exclusive_scan(c, swave, V);
   bcnt[tid] = c;
@@ -485,6 +533,9 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
           ++kept;
         }
       }
+      // a point-list child becomes a hood: the serial strip hood of its
+      // surviving points (the paper's serial hoods of small strips)
+      if (pts && kept > 0) kept = chain_inplace(bxy + o, bid + o, kept, oc, fe);
       // leaves: the non-empty children, in order, 64 per wave
       const uint64_t ne = __ballot(kept > 0);
       if (kept > 0)
@@ -536,6 +587,11 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   }
 
   // ---- too large for LDS: the same rounds in place in the workspace
+  if (pts && c > 0) {  // point-list children first become hoods, in place
+    const int64_t g = child_off[it.child0 + tid];
+    bcnt[tid] = chain_inplace(A.ws_xy + g, A.ws_idx + g, c, oc, fe);
+  }
+  __syncthreads();
 #pragma unroll 1
   for (int j = 0; (1 << j) < nch; ++j) {
     const int M = npow >> (j + 1);
