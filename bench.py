@@ -246,7 +246,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_points": N, "sets": S, "strip": args.strip,
-                   "tile_points": 256 * args.strip, "launches_per_step": plan.launches,
+                   "tile_points": 64 * args.strip, "launches_per_step": plan.launches,
                    "graph": bool(args.graph), "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),
                    "fallback_rate": (fallbacks / evals) if evals else 0.0,

@@ -142,22 +142,67 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Wave-level inclusive max scans (prefix: lanes below; suffix: lanes above).
-__device__ __forceinline__ float wave_prefix_max(float v) {
-  const int lane = threadIdx.x & 63;
-  for (int o = 1; o < 64; o <<= 1) {
-    const float y = __shfl_up(v, o, 64);
-    if (lane >= o) v = fmaxf(v, y);
-  }
+// ---- lane moves inside the VALU (DPP, GFX9 encodings); a lane whose source
+// lies outside its row (or the wave) keeps `old`.
+enum : int {
+  DPP_ROW_SHL = 0x100,       // + n: lane i <- lane i + n of the same row of 16
+  DPP_ROW_SHR = 0x110,       // + n: lane i <- lane i - n of the same row
+  DPP_WAVE_SHL1 = 0x130,     // lane i <- lane i + 1
+  DPP_WAVE_SHR1 = 0x138,     // lane i <- lane i - 1
+  DPP_ROW_HALF_MIRROR = 0x141,
+  DPP_ROW_BCAST15 = 0x142,   // lane 15 of each row -> the next row
+  DPP_ROW_BCAST31 = 0x143,   // lane 31 -> rows 2 and 3
+  DPP_QUAD_XOR1 = 0xB1,      // quad_perm [1, 0, 3, 2]
+  DPP_QUAD_XOR2 = 0x4E,      // quad_perm [2, 3, 0, 1]
+};
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v),
+                                                    CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Inclusive max over the lanes of each row of 16 at or below (prefix) or at
+// or above (suffix) this lane; `id` is below every value.
+__device__ __forceinline__ float row_prefix_max(float v, float id) {
+  v = fmaxf(v, dpp<DPP_ROW_SHR + 1>(id, v));
+  v = fmaxf(v, dpp<DPP_ROW_SHR + 2>(id, v));
+  v = fmaxf(v, dpp<DPP_ROW_SHR + 4>(id, v));
+  v = fmaxf(v, dpp<DPP_ROW_SHR + 8>(id, v));
   return v;
 }
-__device__ __forceinline__ float wave_suffix_max(float v) {
-  const int lane = threadIdx.x & 63;
-  for (int o = 1; o < 64; o <<= 1) {
-    const float y = __shfl_down(v, o, 64);
-    if (lane + o < 64) v = fmaxf(v, y);
-  }
+__device__ __forceinline__ float row_suffix_max(float v, float id) {
+  v = fmaxf(v, dpp<DPP_ROW_SHL + 1>(id, v));
+  v = fmaxf(v, dpp<DPP_ROW_SHL + 2>(id, v));
+  v = fmaxf(v, dpp<DPP_ROW_SHL + 4>(id, v));
+  v = fmaxf(v, dpp<DPP_ROW_SHL + 8>(id, v));
   return v;
+}
+
+// Wave-level inclusive max scans (prefix: lanes below; suffix: lanes above).
+__device__ __forceinline__ float wave_prefix_max(float v, float id = -2.0f) {
+  v = row_prefix_max(v, id);
+  v = fmaxf(v, dpp<DPP_ROW_BCAST15, 0xa>(id, v));  // rows 1, 3 take rows 0, 2
+  v = fmaxf(v, dpp<DPP_ROW_BCAST31, 0xc>(id, v));  // rows 2, 3 take rows 0-1
+  return v;
+}
+__device__ __forceinline__ float wave_suffix_max(float v, float id = -2.0f) {
+  v = row_suffix_max(v, id);
+  // each row's total now sits in its first lane; add those of later rows
+  const float t1 = readlane(v, 16), t2 = readlane(v, 32), t3 = readlane(v, 48);
+  const float t23 = fmaxf(t2, t3), t123 = fmaxf(t1, t23);
+  const int row = (threadIdx.x & 63) >> 4;
+  return fmaxf(v, row == 0 ? t123 : row == 1 ? t23 : row == 2 ? t3 : id);
+}
+
+// Number of set bits of m in the lanes below this one.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Adds a wave's orientation counters to stats[set].
@@ -178,24 +223,30 @@ __device__ __forceinline__ int wave_min(int v) {
 
 // Tile kernel: one wave (one workgroup of 64 lanes) per tile of up to
 // T = 64 * K points of one set; no workgroup barrier anywhere.
-//  1. coalesced 16-byte loads (two points per lane per load), the data
-//     contract's range and grid checks, then the points go to per-lane
-//     strips of K consecutive points in LDS (stride K + 2: 16-byte aligned)
-//     and each lane reads its strip back into registers;
+//  1. coalesced 16-byte loads (two points per lane per load) and the data
+//     contract's checks, then the points go to per-lane strips of K
+//     consecutive points in LDS (stride K + 2: 16-byte aligned) and each lane
+//     reads its strip back into registers.  A partial tile is padded with
+//     points right of and below every valid point, which no test keeps;
 //  2. strip pass 1: maximum y of each strip, x non-decreasing check (the
 //     previous strip's last point comes from the neighbouring lane); wave
 //     prefix and suffix maxima over the strips;
-//  3. strip pass 2: exact elimination, then the strip hood.  A point r is
-//     dropped when some earlier point of the tile is at least as high and
-//     some later point is strictly higher: r then lies below the segment
-//     joining the first earlier maximum and the last later maximum (both of
-//     which survive), or directly below a point at its x, so it is no corner
-//     of the tile's hood (nor is any identical copy of it that survives only
-//     because it comes later).  The survivors go through a serial monotone
-//     chain whose stack lives in the strip's LDS slot (the serial strip
-//     hoods of the paper's work-optimal variant);
-//  4. six rounds of Wagener merges (match-and-merge on adjacent hoods,
-//     block size K * 2^j -> K * 2^(j+1)), the 2^(j+1) lanes of each merge
+//  3. exact elimination.  A point r is dropped when some earlier point of
+//     the set is at least as high and some later point is strictly higher:
+//     r then lies below the segment joining the first earlier maximum and
+//     the last later maximum (both of which survive), or directly below a
+//     point at its x, so it is no corner of the hood (nor is any identical
+//     copy of it that survives only because it comes later).  Witnesses are
+//     the tile's points and 16 points on either side of it.  Only a strip
+//     whose maximum beats every earlier strip, or reaches the maximum of
+//     every later one, can hold a survivor; with strips of 16, four such
+//     strips at a time are tested point by point by the 16 lanes of one
+//     row each.  Few survivors go out as a sorted point list (the merge
+//     kernel makes it a hood); otherwise
+//  4. the survivors of each strip go through a serial monotone chain whose
+//     stack lives in the strip's LDS slot (the serial strip hoods of the
+//     paper's work-optimal variant), then up to six rounds of Wagener merges
+//     (match-and-merge on adjacent hoods), the 2^(j+1) lanes of each merge
 //     acting as the paper's d1 x d2 thread block;
 //  5. the tile's hood goes to the workspace, or to the output for a
 //     one-tile set.
@@ -204,6 +255,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
                                                   int32_t *cnt_out) {
   constexpr int S = K + 2;
   constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
+  constexpr float PAD_X = 2.0f, PAD_Y = -4.0f;  // right of / below every valid point
   __shared__ __attribute__((aligned(16))) float2 sxy[64 * S];
   __shared__ uint16_t sid[64 * S];
   __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
@@ -218,14 +270,13 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   // ---- 1. load
   float4 v[NV];
   int err = 0;
+  bool bad = false;  // some check failed, or the quick checks cannot vouch
   float prev_tile_x = -1.0f;  // below every valid x
   if (validate && lane == 0 && it.start > sstart) prev_tile_x = A.pts[it.start - 1].x;
   // Witnesses from the neighbouring tiles of the same set: the maximum y of
   // up to 16 points just before the tile and of up to 16 just after it
-  // (lanes 0-15 fetch them, two points each).  Any earlier / later point of
-  // the set may serve the elimination test below, and these let the first
-  // and last strips drop their points too.
-  float nb_before = -2.0f, nb_after = -2.0f;
+  // (lanes 0-15 fetch them, two points each).
+  float nb_before, nb_after;
   {
     const int64_t send = A.set_start[it.set + 1];
     float wy = -2.0f;
@@ -237,40 +288,57 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       if (e + 1 < send) wy = fmaxf(A.pts[e].y, A.pts[e + 1].y);
       else if (e < send) wy = A.pts[e].y;
     }
-    for (int o = 4; o > 0; o >>= 1) wy = fmaxf(wy, __shfl_xor(wy, o, 64));
-    nb_before = __shfl(wy, 0, 64);
-    nb_after = __shfl(wy, 8, 64);
+    // maximum over each group of 8 lanes, then read from lanes 0 and 8
+    wy = fmaxf(wy, dpp<DPP_QUAD_XOR1>(wy, wy));
+    wy = fmaxf(wy, dpp<DPP_QUAD_XOR2>(wy, wy));
+    wy = fmaxf(wy, dpp<DPP_ROW_HALF_MIRROR>(wy, wy));
+    nb_before = readlane(wy, 0);
+    nb_after = readlane(wy, 8);
   }
   if (it.len == 64 * K && (((uintptr_t)src) & 15u) == 0) {
     // full, 16-byte aligned tile (the common case): no per-element tests
     const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
 #pragma unroll
     for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
-    bool range_ok = true;
-    float frac = 0.0f;  // sum of fractions of coordinate * 2^30: 0 iff all on grid
+    if (validate) {
+      // Quick checks that can only err towards `bad`: |y| <= 1 (NaN fails
+      // the grid test instead), y * 2^30 without fraction (the bits of a
+      // zero fraction are zero), x within [0, 1] at the tile's ends (the
+      // strip pass checks x non-decreasing, NaN included), and x on the grid:
+      // if the first x is at least 2^-7, every x is, and float32 spacing
+      // there is at least 2^-30.
+      float ry = 0.0f;
+      uint32_t gy = 0u;
+#pragma unroll
+      for (int r = 0; r < NV; ++r) {
+        ry = fmaxf(ry, fmaxf(__builtin_fabsf(v[r].y), __builtin_fabsf(v[r].w)));
+        gy |= __float_as_uint(__builtin_amdgcn_fractf(v[r].y * 0x1p30f)) |
+              __float_as_uint(__builtin_amdgcn_fractf(v[r].w * 0x1p30f));
+      }
+      const float x_first = readlane(v[0].x, 0), x_last = readlane(v[NV - 1].z, 63);
+      bad = !(ry <= 1.0f) || gy != 0u || !(x_first >= 0.0f) || !(x_last <= 1.0f);
+      if (!(x_first >= 0x1p-7f)) {
+        uint32_t gx = 0u;
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+          gx |= __float_as_uint(__builtin_amdgcn_fractf(v[r].x * 0x1p30f)) |
+                __float_as_uint(__builtin_amdgcn_fractf(v[r].z * 0x1p30f));
+        bad = bad || gx != 0u;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
-      if (validate) {
-        range_ok = range_ok && __builtin_fabsf(v[r].x - 0.5f) <= 0.5f &&
-                   __builtin_fabsf(v[r].z - 0.5f) <= 0.5f && __builtin_fabsf(v[r].y) <= 1.0f &&
-                   __builtin_fabsf(v[r].w) <= 1.0f;
-        frac += (__builtin_amdgcn_fractf(v[r].x * 0x1p30f) +
-                 __builtin_amdgcn_fractf(v[r].y * 0x1p30f)) +
-                (__builtin_amdgcn_fractf(v[r].z * 0x1p30f) +
-                 __builtin_amdgcn_fractf(v[r].w * 0x1p30f));
-      }
       float4 *d = reinterpret_cast<float4 *>(
           __builtin_assume_aligned(sxy + (e / K) * S + (e % K), 16));
       *d = v[r];
     }
-    if (!range_ok) err = UH_ERR_RANGE;
-    else if (frac != 0.0f) err = UH_ERR_GRID;
   } else {
     const bool al = (((uintptr_t)src) & 15u) == 0;
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
+      v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
       if (e + 1 < it.len) {
         if (al) {
           v[r] = *reinterpret_cast<const float4 *>(src + e);
@@ -280,24 +348,20 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
         }
       } else if (e < it.len) {
         const float2 a = src[e];
-        v[r] = make_float4(a.x, a.y, 0.f, 0.f);
+        v[r].x = a.x;
+        v[r].y = a.y;
       }
     }
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
-      if (e < it.len) {
-        float2 *d = sxy + (e / K) * S + (e % K);
-        if (validate) {
-          err = min(err, check_point(make_float2(v[r].x, v[r].y)));
-          if (e + 1 < it.len) err = min(err, check_point(make_float2(v[r].z, v[r].w)));
-        }
-        if (e + 1 < it.len)
-          *reinterpret_cast<float4 *>(d) = v[r];
-        else
-          *d = make_float2(v[r].x, v[r].y);
+      if (validate) {
+        if (e < it.len) err = min(err, check_point(make_float2(v[r].x, v[r].y)));
+        if (e + 1 < it.len) err = min(err, check_point(make_float2(v[r].z, v[r].w)));
       }
+      *reinterpret_cast<float4 *>(sxy + (e / K) * S + (e % K)) = v[r];
     }
+    bad = err != 0;
   }
   wave_sync();
   const int my_len = min(max(it.len - lane * K, 0), K);
@@ -313,71 +377,137 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
 
   // ---- 2. strip pass 1
   OrientCount oc;
-  float ymax = -2.0f;  // below every valid y
+  float ymax = PAD_Y;
   {
-    float px = __shfl_up(p[K - 1].x, 1, 64);  // last point of the previous strip
-    if (lane == 0) px = prev_tile_x;
+    // last point of the previous strip (lane 0: of the previous tile)
+    const float px0 = dpp<DPP_WAVE_SHR1>(prev_tile_x, p[K - 1].x);
+    float px = px0;
+    bool uns = false;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      if (i < my_len) {
-        ymax = fmaxf(ymax, p[i].y);
-        if (validate && p[i].x < px) err = min(err, UH_ERR_UNSORTED);
-        px = p[i].x;
+      ymax = fmaxf(ymax, p[i].y);
+      uns = uns || !(p[i].x >= px);
+      px = p[i].x;
+    }
+    if (validate && __ballot(bad || uns)) {
+      // something is off in this tile: the exact error codes, point by point
+      err = 0;
+      px = px0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        if (i < my_len) {
+          err = min(err, check_point(p[i]));
+          if (p[i].x < px) err = min(err, UH_ERR_UNSORTED);
+          px = p[i].x;
+        }
       }
     }
   }
   const float incp = wave_prefix_max(ymax), incs = wave_suffix_max(ymax);
-  float exp_pre = __shfl_up(incp, 1, 64), exp_suf = __shfl_down(incs, 1, 64);
-  if (lane == 0) exp_pre = -2.0f;
-  if (lane == 63) exp_suf = -2.0f;
-  exp_pre = fmaxf(exp_pre, nb_before);
-  exp_suf = fmaxf(exp_suf, nb_after);
+  const float exp_pre = fmaxf(dpp<DPP_WAVE_SHR1>(-2.0f, incp), nb_before);  // earlier strips
+  const float exp_suf = fmaxf(dpp<DPP_WAVE_SHL1>(-2.0f, incs), nb_after);   // later strips
+  const int rel0 = (int)(it.start - sstart);
 
-  // ---- 3. strip pass 2: elimination (from registers)
+  // ---- 3. elimination; few survivors leave as a point list
+  if (K == 16 && !it.final_) {
+    const uint64_t cand = __ballot(ymax > exp_pre || ymax >= exp_suf);
+    const int ncand = __builtin_popcountll(cand);
+    if (ncand <= 16) {
+      // each row of 16 lanes takes one candidate strip per pass; lane i of
+      // the row tests point i against the exact earlier / later maxima
+      reinterpret_cast<float2 *>(sblk)[lane] = make_float2(exp_pre, exp_suf);
+      wave_sync();
+      const int row = lane >> 4, i = lane & 15;
+      const int npass = (ncand + 3) >> 2;
+      uint64_t rest = cand, kb[4];
+      float2 kp[4];
+      int kid[4], nsurv = 0;
+#pragma unroll
+      for (int ps = 0; ps < 4; ++ps) {
+        kb[ps] = 0;
+        kp[ps] = make_float2(0.f, 0.f);
+        kid[ps] = 0;
+        if (ps < npass) {
+          int Ls[4];
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            Ls[rr] = rest ? (int)__builtin_ctzll(rest) : -1;
+            rest &= rest - 1;
+          }
+          const int L = row == 0 ? Ls[0] : row == 1 ? Ls[1] : row == 2 ? Ls[2] : Ls[3];
+          const int Lc = L < 0 ? 0 : L;
+          const float2 q = sxy[Lc * S + i];
+          const float2 w = reinterpret_cast<const float2 *>(sblk)[Lc];
+          const float before = fmaxf(w.x, dpp<DPP_ROW_SHR + 1>(-2.0f, row_prefix_max(q.y, -2.0f)));
+          const float after = fmaxf(w.y, dpp<DPP_ROW_SHL + 1>(-2.0f, row_suffix_max(q.y, -2.0f)));
+          const bool keep = L >= 0 && (q.y > before || q.y >= after);
+          kb[ps] = __ballot(keep);
+          kp[ps] = q;
+          kid[ps] = Lc * K + i;
+          nsurv += __builtin_popcountll(kb[ps]);
+        }
+      }
+      if (nsurv <= TILE_LIST_MAX) {
+        int base = 0;
+#pragma unroll
+        for (int ps = 0; ps < 4; ++ps) {
+          if ((kb[ps] >> lane) & 1ull) {
+            const int r = base + lanes_below(kb[ps]);
+            A.ws_xy[it.start + r] = kp[ps];
+            A.ws_idx[it.start + r] = rel0 + kid[ps];
+          }
+          base += __builtin_popcountll(kb[ps]);
+        }
+        if (lane == 0) cnt_out[blockIdx.x] = (int)((uint32_t)nsurv | POINTS_FLAG);
+        if (err) atomicMin(&A.set_status[it.set], err);
+        flush_wave_stats(A, it.set, oc);
+        return;
+      }
+      wave_sync();  // the hood path below reuses sblk
+    }
+  }
   uint32_t keep = 0;
   {
-    float bm = exp_pre;  // max y over earlier points of the tile
+    float bm = exp_pre;  // max y over earlier points of the set
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      if (i < my_len && (p[i].y > bm || p[i].y >= exp_suf)) keep |= 1u << i;
+      if (p[i].y > bm || p[i].y >= exp_suf) keep |= 1u << i;
       bm = fmaxf(bm, p[i].y);
     }
   }
-  // Survivors of the whole wave, counted and ranked by a wave prefix sum.
-  const int nk = __builtin_popcount(keep);
-  int koff = nk;  // inclusive prefix sum of nk over the lanes
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(koff, o, 64);
-    if (lane >= o) koff += y;
-  }
-  const int nsurv = __shfl(koff, 63, 64);
-  koff -= nk;
-  int nleaf;
-  if (!it.final_ && nsurv <= TILE_LIST_MAX) {
-    // Few survivors: hand them on, in order, as a point list; the merge
-    // kernel turns them into a hood after eliminating across many tiles.
-    err = wave_min(err);
-    const int rel0 = (int)(it.start - sstart);
-    int r = koff;
+  if constexpr (K != 16) {
+    // survivor list for the other strip widths: ranks by a wave prefix sum
+    const int nk = __builtin_popcount(keep);
+    int koff = nk;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(koff, o, 64);
+      if (lane >= o) koff += y;
+    }
+    const int nsurv = __shfl(koff, 63, 64);
+    koff -= nk;
+    if (!it.final_ && nsurv <= TILE_LIST_MAX) {
+      int r = koff;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      if ((keep >> i) & 1u) {
-        A.ws_xy[it.start + r] = p[i];
-        A.ws_idx[it.start + r] = rel0 + lane * K + i;
-        ++r;
+      for (int i = 0; i < K; ++i) {
+        if ((keep >> i) & 1u) {
+          A.ws_xy[it.start + r] = p[i];
+          A.ws_idx[it.start + r] = rel0 + lane * K + i;
+          ++r;
+        }
       }
-    }
-    if (lane == 0) {
-      cnt_out[blockIdx.x] = (int)((uint32_t)nsurv | POINTS_FLAG);
+      if (lane == 0) cnt_out[blockIdx.x] = (int)((uint32_t)nsurv | POINTS_FLAG);
       if (err) atomicMin(&A.set_status[it.set], err);
+      flush_wave_stats(A, it.set, oc);
+      return;
     }
-    flush_wave_stats(A, it.set, oc);
-    return;
-  } else {
-    // Many survivors: the serial strip hood over each strip's survivors
-    // (re-read from LDS; the stack overwrites the slot from its start,
-    // never past a survivor still to be read), then the non-empty strip
-    // hoods are the leaves.
+  }
+
+  // ---- 4. strip hoods, then rounds of Wagener merges over them
+  int nleaf;
+  {
+    // the serial strip hood over each strip's survivors (re-read from LDS;
+    // the stack overwrites the slot from its start, never past a survivor
+    // still to be read); the non-empty strip hoods are the leaves
     int cnt = 0;
     float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
     while (keep) {
@@ -401,23 +531,19 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       t1 = r;
       ++cnt;
     }
-    // Leaves of the merge tree: the non-empty strip hoods, in order.
     // Nothing between two consecutive leaves survived, so merging
     // neighbouring leaves is merging hoods of x-adjacent point sets.
     const uint64_t ne = __ballot(cnt > 0);
     nleaf = __builtin_popcountll(ne);
-    if (cnt > 0) sblk[__builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(lane * S, cnt);
+    if (cnt > 0) sblk[lanes_below(ne)] = make_int2(lane * S, cnt);
     wave_sync();
   }
-
-  // ---- 4. rounds of Wagener merges over the leaves
   wave_rounds(sxy, sid, sblk, nleaf, oc, fe);
 
   // ---- 5. output
-  err = wave_min(err);
   const int hb = nleaf ? sblk[0].x : 0, hc = nleaf ? sblk[0].y : 0;
-  const int rel0 = (int)(it.start - sstart);
   if (it.final_) {
+    if (__ballot(err != 0)) err = wave_min(err);
     int32_t *dst = A.out_idx + sstart;
     for (int k = lane; k < hc; k += 64) dst[k] = rel0 + (int)sid[hb + k];
     if (lane == 0) A.out_counts[it.set] = err ? err : hc;
@@ -426,10 +552,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       A.ws_xy[it.start + k] = sxy[hb + k];
       A.ws_idx[it.start + k] = rel0 + (int)sid[hb + k];
     }
-    if (lane == 0) {
-      cnt_out[blockIdx.x] = hc;
-      if (err) atomicMin(&A.set_status[it.set], err);
-    }
+    if (lane == 0) cnt_out[blockIdx.x] = hc;
+    if (err) atomicMin(&A.set_status[it.set], err);
   }
   flush_wave_stats(A, it.set, oc);
 }
@@ -469,7 +593,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   __shared__ int bcnt[BLOCK];
   __shared__ int2 sblk[BLOCK];  // LDS path: (base, count) per child block
   __shared__ int2 sres[BLOCK / 2];
-  __shared__ int swave[BLOCK / 64];
+  __shared__ int swave[BLOCK / 64 + 1];
   __shared__ int smax;
 
   const MergeItem it = items[blockIdx.x];
@@ -491,12 +615,26 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   __syncthreads();
 
   if (V <= VMAX) {
-    // ---- gather: thread k copies child k's corners (independent loads)
+    // ---- gather: thread k copies child k's corners, eight loads in flight
     if (tid < nch) {
       const int64_t g = child_off[it.child0 + tid];
-      for (int e = 0; e < c; ++e) {
-        bxy[o + e] = A.ws_xy[g + e];
-        bid[o + e] = A.ws_idx[g + e];
+      for (int e0 = 0; e0 < c; e0 += 8) {
+        float2 vx[8];
+        int32_t vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (e0 + u < c) {
+            vx[u] = A.ws_xy[g + e0 + u];
+            vi[u] = A.ws_idx[g + e0 + u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (e0 + u < c) {
+            bxy[o + e0 + u] = vx[u];
+            bid[o + e0 + u] = vi[u];
+          }
+        }
       }
     }
     __syncthreads();
@@ -536,36 +674,56 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
       // a point-list child becomes a hood: the serial strip hood of its
       // surviving points (the paper's serial hoods of small strips)
       if (pts && kept > 0) kept = chain_inplace(bxy + o, bid + o, kept, oc, fe);
-      // leaves: the non-empty children, in order, 64 per wave
+      // leaves: the non-empty children, in order
       const uint64_t ne = __ballot(kept > 0);
-      if (kept > 0)
-        sblk[(w << 6) + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
       if (lane == 0) swave[w] = __builtin_popcountll(ne);
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int k = 0; k < BLOCK / 64; ++k) {
+        before += k < w ? swave[k] : 0;
+        total += swave[k];
+      }
+      if (total <= 64) {  // all leaves to wave 0's rounds, back to back
+        if (kept > 0)
+          sblk[before + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
+      } else {            // 64 leaf slots per wave, then wave 0 joins them
+        if (kept > 0)
+          sblk[(w << 6) + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
+      }
+      if (tid == 0) swave[BLOCK / 64] = total;
     }
     __syncthreads();
-    wave_rounds(bxy, bid, sblk + (w << 6), swave[w], oc, fe);
+    const int total_leaves = swave[BLOCK / 64];
+    if (total_leaves > 64) wave_rounds(bxy, bid, sblk + (w << 6), swave[w], oc, fe);
     __syncthreads();
     if (w == 0) {
-      // the wave hoods (one per wave that had leaves), left to right
-      int nb0 = 0, nc0 = 0;
-      bool have = false;
-      for (int k = 0; k < BLOCK / 64; ++k) {
-        if (swave[k] == 0) continue;
-        const int2 Q = sblk[k << 6];
-        if (!have) {
-          nb0 = Q.x;
-          nc0 = Q.y;
-          have = true;
-          continue;
-        }
-        int nb, nc;
-        merge_blocks(bxy, bid, nb0, nc0, Q.x, Q.y, 6, lane, 0, nb, nc, oc, fe);
+      if (total_leaves == 0) {  // every child empty (possible on invalid data)
+        if (lane == 0) sblk[0] = make_int2(0, 0);
         wave_sync();
-        nb0 = nb;
-        nc0 = nc;
+      } else if (total_leaves <= 64) {
+        wave_rounds(bxy, bid, sblk, total_leaves, oc, fe);
+      } else {
+        // the wave hoods (one per wave that had leaves), left to right
+        int nb0 = 0, nc0 = 0;
+        bool have = false;
+        for (int k = 0; k < BLOCK / 64; ++k) {
+          if (swave[k] == 0) continue;
+          const int2 Q = sblk[k << 6];
+          if (!have) {
+            nb0 = Q.x;
+            nc0 = Q.y;
+            have = true;
+            continue;
+          }
+          int nb, nc;
+          merge_blocks(bxy, bid, nb0, nc0, Q.x, Q.y, 6, lane, 0, nb, nc, oc, fe);
+          wave_sync();
+          nb0 = nb;
+          nc0 = nc;
+        }
+        if (lane == 0) sblk[0] = make_int2(nb0, nc0);
+        wave_sync();
       }
-      if (lane == 0) sblk[0] = make_int2(nb0, nc0);
-      wave_sync();
       const int hb = sblk[0].x, hc = sblk[0].y;
       if (it.final_) {
         int32_t *dst = A.out_idx + A.set_start[it.set];

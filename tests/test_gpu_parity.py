@@ -121,11 +121,12 @@ def test_random_lattices_batched(side):
 
 
 # ------------------------------------------------------------ tiles / rounds
-TILE = 4096
+TILE = 64 * 16  # points per tile of the default plan (64 lanes x strip 16)
+GROUP = 256 * TILE  # points under one first-pass merge workgroup (fan-in 256)
 
 
 @pytest.mark.parametrize("n", [TILE - 1, TILE, TILE + 1, 2 * TILE - 1, 2 * TILE + 1,
-                               7 * TILE + 3, 256 * TILE + 5])
+                               7 * TILE + 3, GROUP + 5, 2 * GROUP + 7])
 def test_sizes_around_tiles(n):
     assert_parity(synth.uniform(n, 22, seed=n))
     assert_parity(synth.arc(min(n, 1 << 20), 20, 4, seed=n + 1))
@@ -164,7 +165,7 @@ def test_concave_all_corners_global_path():
 def test_equal_x_runs_across_tiles():
     n = 5 * TILE
     X = np.arange(n, dtype=np.int64)
-    X[TILE - 3000: 3 * TILE + 100] = TILE - 3000  # one run spanning three tiles
+    X[TILE - 300: 3 * TILE + 100] = TILE - 300  # one run spanning three tiles
     X = np.sort(X)
     rng = np.random.default_rng(4)
     Y = rng.integers(0, 1 << 20, n)
@@ -232,6 +233,30 @@ def test_data_errors_reported_per_set():
     assert c == uh.UH_ERR_UNSORTED
     c, _ = gpu_hull(grid_bad[:50])
     assert c == uh.UH_ERR_GRID
+
+
+def test_sets_whose_points_are_all_eliminated():
+    # NaN heights fail every elimination test, so whole tiles, and whole
+    # merge workgroups, end up with no surviving point: the merges must
+    # still write consistent (empty) hoods and report the error, and the
+    # valid sets around them must be unaffected.
+    good = synth.uniform(300000, 22, seed=4)
+    sets = []
+    for n in (2 * TILE, 600000):
+        bad = synth.uniform(n, 22, seed=n)
+        bad[:, 1] = np.nan
+        sets += [good, bad]
+    half = good.copy()
+    half[150000:, 1] = np.nan  # a valid left half, an eliminated right half
+    sets += [half, good]
+    pts, off = synth.concat_sets(sets)
+    out, cnt = gpu_batched(pts, off)
+    ref = oracle.upper_hull(good)
+    for s in (0, 2, 5):
+        assert cnt[s] == len(ref)
+        assert np.array_equal(out[off[s]:off[s] + cnt[s]], ref)
+    assert cnt[1] == uh.UH_ERR_RANGE and cnt[3] == uh.UH_ERR_RANGE
+    assert cnt[4] == uh.UH_ERR_RANGE
 
 
 def test_argument_errors():
