@@ -273,10 +273,6 @@ __device__ __forceinline__ void group_move(float2 *xy, ID *id, int src, int dst,
   }
 }
 
-// Hoods at most this long are merged by the corner test instead of the
-// sampled search.
-constexpr int SMALL_HOOD = 8;
-
 // Merge (match-and-merge, mam1-mam6) of two adjacent hoods stored in one LDS
 // region: P = [bp, bp + hp) and Q = [bq, bq + hq), bp + hp <= bq, run by the
 // G <= 64 lanes of one group of one wave.  The merged hood
@@ -285,6 +281,12 @@ constexpr int SMALL_HOOD = 8;
 // Also applies the vertical-closure rule at the junction: if P's last and
 // Q's first corner share x, only the higher survives (ties: P's, the lower
 // index).
+//
+// The bridge (a, b) is the one pair of corners that are each other's tangent
+// corner: g(P[a], Q[b]) and f(Q[b], P[a]) are both EQUAL (the stopping
+// condition of mam5; with the tie rules of g and f the pair is unique).
+// When hp * hq is at most 4 G, every pair is classified directly, G pairs at
+// a time, one pair per lane; larger hoods use the sampled search.
 template <class ID>
 __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
                                              int bq, int hq, int lgG, int t, int gbase,
@@ -315,42 +317,30 @@ __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
     return;
   }
   int a = hp - 1, b = 0;
-  if (hp <= SMALL_HOOD && hq <= SMALL_HOOD) {
-    // Small hoods: each corner decides whether it stays, by the definition of
-    // a strict corner of the union -- P[i] stays iff i == 0 or every Q corner
-    // is strictly below the line P[i-1] -> P[i]; Q[j] stays iff j is last or
-    // every P corner is strictly below the line Q[j] -> Q[j+1].  The kept
-    // corners are exactly P[0..a] and Q[b..] for the bridge (a, b), so
-    // counting them gives both ends.  Lane t takes corners t, t + G, ...
-    int nkp = 0, nkq = 0;
-    for (int c0 = 0; c0 < hp + hq; c0 += G) {
-      const int c = c0 + t;
-      bool keep = false;
-      if (c < hp) {
-        keep = true;
-        if (c > 0) {
-          const float2 p0 = xy[bp + c - 1], p1 = xy[bp + c];
-          for (int k = 0; k < hq && keep; ++k)
-            keep = orient_sign(p0, p1, xy[bq + k], oc, fe) < 0;
-        }
-      } else if (c < hp + hq) {
-        const int j = c - hp;
-        keep = true;
-        if (j + 1 < hq) {
-          const float2 q0 = xy[bq + j], q1 = xy[bq + j + 1];
-          for (int k = 0; k < hp && keep; ++k)
-            keep = orient_sign(q0, q1, xy[bp + k], oc, fe) < 0;
-        }
+  const int npair = hp * hq;
+  if (npair <= 4 * G) {
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+    // pair r = i * hq + j; i = floor((r + 1/2) / hq) in FP32 is exact here
+    // (r < 256: the quotient stays at least 1/(2 hq) away from an integer)
+    const float rq = 1.0f / (float)hq;
+    for (int r0 = 0; r0 < npair; r0 += G) {
+      const int r = r0 + t;
+      bool hit = false;
+      int i = 0, j = 0;
+      if (r < npair) {
+        i = (int)(((float)r + 0.5f) * rq);
+        j = r - i * hq;
+        hit = g_classify(xy[bp + i], xy + bq, j, hq, oc, fe) == EQUAL &&
+              f_classify(xy[bq + j], xy + bp, i, hp, oc, fe) == EQUAL;
       }
-      const uint64_t m = (__ballot(keep) >> gbase) & (G == 64 ? ~0ull : ((1ull << G) - 1ull));
-      // lanes of this round holding P corners: t < hp - c0
-      const int np_lanes = min(max(hp - c0, 0), G);
-      const uint64_t pm = np_lanes == 64 ? ~0ull : ((1ull << np_lanes) - 1ull);
-      nkp += __builtin_popcountll(m & pm);
-      nkq += __builtin_popcountll(m & ~pm);
+      const uint64_t m = (__ballot(hit) >> gbase) & gmask;
+      if (m) {
+        const int k = r0 + __builtin_ctzll(m);
+        a = (int)(((float)k + 0.5f) * rq);
+        b = k - a * hq;
+        break;
+      }
     }
-    a = nkp - 1;
-    b = hq - nkq;
   } else {
     bridge_search<const float2 *>(xy + bp, hp, xy + bq, hq, G, t, gbase, a, b, oc, fe);
   }

@@ -43,7 +43,7 @@
 namespace uh {
 
 constexpr int BLOCK = 256;       // threads per workgroup (4 waves)
-constexpr int VMAX = 8192;       // corners a merge workgroup keeps in LDS
+constexpr int VMAX = 6144;       // corners a merge workgroup keeps in LDS (two per CU)
 // Bit 31 of a tile's output count: the tile wrote its surviving points (a
 // sorted point list, not yet a hood); the merge kernel makes it a hood.
 constexpr uint32_t POINTS_FLAG = 0x80000000u;
@@ -59,6 +59,7 @@ struct TileItem {    // one tile of the tile pass
 
 struct MergeItem {   // one workgroup of a merge pass
   int64_t off;       // slot start = first child's slot start (absolute)
+  int64_t stride;    // child k's slot starts at off + k * stride
   int32_t child0;    // first child in the previous level's arrays
   int32_t nch;       // children, 2 .. F
   int32_t set;
@@ -74,6 +75,7 @@ struct RunArgs {
   int32_t *out_idx;
   int32_t *out_counts;
   upper_hull_stats *stats;   // [S] or null
+  int64_t n_total;           // points over all sets (workspace length)
   uint32_t flags;
 };
 
@@ -260,7 +262,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   __shared__ uint16_t sid[64 * S];
   __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
 
-  const TileItem it = items[blockIdx.x];
+  const int tile = blockIdx.x;
+  const TileItem it = items[tile];
   const int lane = threadIdx.x;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
@@ -458,9 +461,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
           }
           base += __builtin_popcountll(kb[ps]);
         }
-        if (lane == 0) cnt_out[blockIdx.x] = (int)((uint32_t)nsurv | POINTS_FLAG);
+        if (lane == 0) cnt_out[tile] = (int)((uint32_t)nsurv | POINTS_FLAG);
         if (err) atomicMin(&A.set_status[it.set], err);
-        flush_wave_stats(A, it.set, oc);
         return;
       }
       wave_sync();  // the hood path below reuses sblk
@@ -495,9 +497,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
           ++r;
         }
       }
-      if (lane == 0) cnt_out[blockIdx.x] = (int)((uint32_t)nsurv | POINTS_FLAG);
+      if (lane == 0) cnt_out[tile] = (int)((uint32_t)nsurv | POINTS_FLAG);
       if (err) atomicMin(&A.set_status[it.set], err);
-      flush_wave_stats(A, it.set, oc);
       return;
     }
   }
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       A.ws_xy[it.start + k] = sxy[hb + k];
       A.ws_idx[it.start + k] = rel0 + (int)sid[hb + k];
     }
-    if (lane == 0) cnt_out[blockIdx.x] = hc;
+    if (lane == 0) cnt_out[tile] = hc;
     if (err) atomicMin(&A.set_status[it.set], err);
   }
   flush_wave_stats(A, it.set, oc);
@@ -586,11 +587,11 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &tota
 // a group of lanes with workgroup barriers between the reads and writes of
 // the compaction.
 __global__ __launch_bounds__(BLOCK) void merge_kernel(
-    RunArgs A, const MergeItem *items, const int64_t *child_off,
-    const int32_t *child_cnt, int32_t *cnt_out) {
+    RunArgs A, const MergeItem *items, const int32_t *child_cnt, int32_t *cnt_out) {
   __shared__ float2 bxy[VMAX];
   __shared__ int32_t bid[VMAX];
   __shared__ int bcnt[BLOCK];
+  __shared__ int soff[BLOCK];
   __shared__ int2 sblk[BLOCK];  // LDS path: (base, count) per child block
   __shared__ int2 sres[BLOCK / 2];
   __shared__ int swave[BLOCK / 64 + 1];
@@ -602,23 +603,53 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const int nch = it.nch;
 
-  // a child is a hood, or (POINTS_FLAG) a tile's sorted surviving points
+  // A child is a hood, or (POINTS_FLAG) a tile's sorted surviving points.
+  // Child k belongs to thread k.  Its count and its first PRE = 16 entries
+  // are fetched together: load u of a wave brings entries 0..15 of four of
+  // the wave's children, 16 consecutive lanes per child (entries past a
+  // count are stale and ignored; indices are clamped to the workspace).
+  constexpr int PRE = 16;
+  const int64_t g = it.off + (int64_t)tid * it.stride;
   const uint32_t craw = tid < nch ? (uint32_t)child_cnt[it.child0 + tid] : 0u;
+  float2 vx[16];
+  int32_t vi[16];
+  {
+    const int64_t last = A.n_total - 1;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int ck = (w << 6) + 4 * u + (lane >> 4);  // child of this load
+      int64_t e = it.off + (int64_t)ck * it.stride + (lane & 15);
+      e = e < last ? e : last;
+      if (ck < nch) {
+        vx[u] = A.ws_xy[e];
+        vi[u] = A.ws_idx[e];
+      }
+    }
+  }
   const bool pts = (craw & POINTS_FLAG) != 0;
   const int c = (int)(craw & ~POINTS_FLAG);
   int V;
   const int o = block_exclusive_scan(c, swave, V);
   bcnt[tid] = c;
+  soff[tid] = o;
   int npow = 1;
   while (npow < nch) npow <<= 1;
   OrientCount oc;
   __syncthreads();
 
   if (V <= VMAX) {
-    // ---- gather: thread k copies child k's corners, eight loads in flight
+    // ---- gather: the prefetched entries to their places, then thread k
+    // copies whatever child k has beyond them, eight loads in flight
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int ck = (w << 6) + 4 * u + (lane >> 4), e = lane & 15;
+      if (ck < nch && e < bcnt[ck]) {
+        bxy[soff[ck] + e] = vx[u];
+        bid[soff[ck] + e] = vi[u];
+      }
+    }
     if (tid < nch) {
-      const int64_t g = child_off[it.child0 + tid];
-      for (int e0 = 0; e0 < c; e0 += 8) {
+      for (int e0 = PRE; e0 < c; e0 += 8) {
         float2 vx[8];
         int32_t vi[8];
 #pragma unroll
@@ -646,7 +677,13 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
     // every child stays a hood.
     {
       float cmax = -2.0f;
-      for (int e = 0; e < c; ++e) cmax = fmaxf(cmax, bxy[o + e].y);
+      for (int e0 = 0; e0 < c; e0 += 8) {  // eight LDS reads in flight
+        float yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) yv[u] = e0 + u < c ? bxy[o + e0 + u].y : -2.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) cmax = fmaxf(cmax, yv[u]);
+      }
       const float incp = wave_prefix_max(cmax), incs = wave_suffix_max(cmax);
       __shared__ float swp[BLOCK / 64], sws[BLOCK / 64];
       if (lane == 63) swp[w] = incp;
@@ -660,15 +697,27 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
         if (k > w) suf = fmaxf(suf, sws[k]);
       }
       int kept = 0;
-      for (int e = 0; e < c; ++e) {
-        const float2 q = bxy[o + e];
-        const bool keep = q.y > pre || q.y >= suf;
-        pre = fmaxf(pre, q.y);
-        if (keep) {
-          const int32_t qi = bid[o + e];
-          bxy[o + kept] = q;
-          bid[o + kept] = qi;
-          ++kept;
+      for (int e0 = 0; e0 < c; e0 += 8) {  // a batch is read before it is rewritten
+        float2 qv[8];
+        int32_t iv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (e0 + u < c) {
+            qv[u] = bxy[o + e0 + u];
+            iv[u] = bid[o + e0 + u];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (e0 + u < c) {
+            const bool keep = qv[u].y > pre || qv[u].y >= suf;
+            pre = fmaxf(pre, qv[u].y);
+            if (keep) {
+              bxy[o + kept] = qv[u];
+              bid[o + kept] = iv[u];
+              ++kept;
+            }
+          }
         }
       }
       // a point-list child becomes a hood: the serial strip hood of its
@@ -745,10 +794,8 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   }
 
   // ---- too large for LDS: the same rounds in place in the workspace
-  if (pts && c > 0) {  // point-list children first become hoods, in place
-    const int64_t g = child_off[it.child0 + tid];
+  if (pts && c > 0)  // point-list children first become hoods, in place
     bcnt[tid] = chain_inplace(A.ws_xy + g, A.ws_idx + g, c, oc, fe);
-  }
   __syncthreads();
 #pragma unroll 1
   for (int j = 0; (1 << j) < nch; ++j) {
@@ -761,7 +808,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
     int32_t *Pid = nullptr, *Qid = nullptr;
     if (tid == 0) smax = 0;
     if (lp < nch && lq < nch) {
-      const int64_t op = child_off[it.child0 + lp], oq = child_off[it.child0 + lq];
+      const int64_t op = it.off + lp * it.stride, oq = it.off + lq * it.stride;
       P = A.ws_xy + op;
       Q = A.ws_xy + oq;
       Pid = A.ws_idx + op;
@@ -866,10 +913,8 @@ struct upper_hull_plan {
   // device memory
   int64_t *d_set_start = nullptr;
   TileItem *d_tiles = nullptr;
-  int64_t *d_tile_off = nullptr;
   int32_t *d_cnt0 = nullptr;
   std::vector<MergeItem *> d_items;
-  std::vector<int64_t *> d_off;   // per pass: item slot offsets
   std::vector<int32_t *> d_cnt;   // per pass: item corner counts
   float2 *ws_xy = nullptr;
   int32_t *ws_idx = nullptr;
@@ -902,10 +947,8 @@ int upload(T *dst, const std::vector<T> &src) {
 void free_plan_memory(upper_hull_plan *p) {
   hipFree(p->d_set_start);
   hipFree(p->d_tiles);
-  hipFree(p->d_tile_off);
   hipFree(p->d_cnt0);
   for (auto *q : p->d_items) hipFree(q);
-  for (auto *q : p->d_off) hipFree(q);
   for (auto *q : p->d_cnt) hipFree(q);
   hipFree(p->ws_xy);
   hipFree(p->ws_idx);
@@ -934,10 +977,9 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
       return UH_ERR_HIP;
   }
   for (size_t ps = 0; ps < p->pass_items.size(); ++ps) {
-    const int64_t *coff = ps == 0 ? p->d_tile_off : p->d_off[ps - 1];
     const int32_t *ccnt = ps == 0 ? p->d_cnt0 : p->d_cnt[ps - 1];
     hipLaunchKernelGGL(merge_kernel, dim3(p->pass_items[ps]), dim3(BLOCK), 0, stream, A,
-                       p->d_items[ps], coff, ccnt, p->d_cnt[ps]);
+                       p->d_items[ps], ccnt, p->d_cnt[ps]);
   }
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
@@ -994,7 +1036,6 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
 
   // level 0: tiles; then merge passes of fan-in F until one hood per set
   std::vector<TileItem> tiles;
-  std::vector<int64_t> tile_off;
   std::vector<int32_t> first(num_sets), count(num_sets);  // blocks per set
   for (int32_t s = 0; s < num_sets; ++s) {
     const int64_t n = set_offsets[s + 1] - set_offsets[s];
@@ -1009,12 +1050,13 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       it.final_ = nt == 1;
       it.pad = 0;
       tiles.push_back(it);
-      tile_off.push_back(it.start);
     }
   }
   p->ntiles = (int32_t)tiles.size();
-  std::vector<int64_t> prev_off = tile_off;
+  // Within a set the blocks of a level are consecutive and equally long
+  // (except the last), so child k of an item starts at off + k * stride.
   std::vector<std::vector<MergeItem>> passes;
+  int64_t stride = p->T;
   for (;;) {
     std::vector<MergeItem> items;
     std::vector<int32_t> nfirst(num_sets), ncount(num_sets);
@@ -1027,7 +1069,8 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
         MergeItem m;
         m.child0 = first[s] + i * F;
         m.nch = std::min(F, count[s] - i * F);
-        m.off = prev_off[m.child0];
+        m.off = set_offsets[s] + (int64_t)i * F * stride;
+        m.stride = stride;
         m.set = s;
         m.final_ = nitems == 1;
         items.push_back(m);
@@ -1035,10 +1078,8 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       ncount[s] = nitems;
     }
     if (items.empty()) break;
-    std::vector<int64_t> off(items.size());
-    for (size_t i = 0; i < items.size(); ++i) off[i] = items[i].off;
     passes.push_back(items);
-    prev_off = off;
+    stride *= F;
     first = nfirst;
     // sets finished in this pass keep count 1 -> no further items
     for (int32_t s = 0; s < num_sets; ++s) count[s] = ncount[s];
@@ -1050,23 +1091,15 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   rc = rc ? rc : upload(p->d_set_start, so);
   rc = rc ? rc : dalloc(&p->d_tiles, tiles.size());
   rc = rc ? rc : upload(p->d_tiles, tiles);
-  rc = rc ? rc : dalloc(&p->d_tile_off, tile_off.size());
-  rc = rc ? rc : upload(p->d_tile_off, tile_off);
   rc = rc ? rc : dalloc(&p->d_cnt0, tiles.size());
   for (auto &items : passes) {
     if (rc) break;
     MergeItem *di = nullptr;
-    int64_t *doff = nullptr;
     int32_t *dcnt = nullptr;
-    std::vector<int64_t> off(items.size());
-    for (size_t i = 0; i < items.size(); ++i) off[i] = items[i].off;
     rc = rc ? rc : dalloc(&di, items.size());
     rc = rc ? rc : upload(di, items);
-    rc = rc ? rc : dalloc(&doff, items.size());
-    rc = rc ? rc : upload(doff, off);
     rc = rc ? rc : dalloc(&dcnt, items.size());
     p->d_items.push_back(di);
-    p->d_off.push_back(doff);
     p->d_cnt.push_back(dcnt);
     p->pass_items.push_back((int32_t)items.size());
   }
@@ -1109,6 +1142,7 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   A.out_idx = out_idx;
   A.out_counts = out_counts;
   A.stats = stats;
+  A.n_total = p->N;
   A.flags = p->flags;
   if (!(p->flags & UH_FLAG_GRAPH)) return enqueue_run(p, A, stream);
 

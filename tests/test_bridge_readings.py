@@ -9,7 +9,11 @@
   (tangent corners nondecreasing) holds for the samples at or left of the
   bridge corner and fails to the right of it, even in general position
   (test_theorem_first_claim_counterexample);
-* the merge P[0..a] ++ Q[b..] equals the hood of the union (the oracle).
+* the merge P[0..a] ++ Q[b..] equals the hood of the union (the oracle);
+* the stopping condition of mam5 read as a test on pairs: exactly one pair
+  (i, j) has g(P[i], Q[j]) = f(Q[j], P[i]) = EQUAL, and it is the bridge
+  defined as the leftmost P-corner and rightmost Q-corner on the common
+  tangent (the merge kernels classify all pairs of small hoods this way).
 """
 import itertools
 import random
@@ -66,6 +70,10 @@ def _check_pair(P, Q):
     # the corner-wise survival test picks exactly P[0..a] and Q[b..]
     kp, kq = B.survivors(P, Q)
     assert kp == list(range(a + 1)) and kq == list(range(b, len(Q))), (P, Q)
+    # the pairs classified EQUAL by both g and f: exactly the bridge
+    mutual = [(i, j) for i in range(len(P)) for j in range(len(Q))
+              if B.g_rule(P[i], Q, j) == B.EQUAL and B.f_rule(Q[j], P, i) == B.EQUAL]
+    assert mutual == [(a, b)], (P, Q, mutual)
 
 
 def test_exhaustive_small_hoods():
