@@ -49,10 +49,13 @@ constexpr int VMAX = 6144;       // corners a merge workgroup keeps in LDS (two 
 constexpr uint32_t POINTS_FLAG = 0x80000000u;
 constexpr int TILE_LIST_MAX = 64;  // most survivors a tile hands on as a list
 
-struct TileItem {    // one tile of the tile pass
+struct TileItem {    // one tile of the tile pass (everything a tile needs: 32 bytes)
   int64_t start;     // first point (absolute)
   int32_t len;       // points, 1 .. T
   int32_t set;
+  int32_t rel0;      // start minus the set's start (set-relative index of the first point)
+  int16_t nb_lo;     // points of the set just before the tile used as witnesses, 0 .. 16
+  int16_t nb_hi;     // points of the set just after it used as witnesses, 0 .. 16
   int32_t final_;    // 1 if this tile is its set's only tile
   int32_t pad;
 };
@@ -267,42 +270,56 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   const int lane = threadIdx.x;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
-  const int64_t sstart = A.set_start[it.set];
   const float2 *src = A.pts + it.start;
 
-  // ---- 1. load
+  // ---- 1. load.  Every load of the tile is issued before the first wait:
+  // the tile's points, then (unconditionally, at clamped addresses) the
+  // witnesses from the neighbouring tiles of the same set -- the maximum y
+  // of up to 16 points just before the tile and of up to 16 just after it
+  // (lanes 0-15, two points each) -- and the set's point before the tile.
   float4 v[NV];
-  int err = 0;
-  bool bad = false;  // some check failed, or the quick checks cannot vouch
-  float prev_tile_x = -1.0f;  // below every valid x
-  if (validate && lane == 0 && it.start > sstart) prev_tile_x = A.pts[it.start - 1].x;
-  // Witnesses from the neighbouring tiles of the same set: the maximum y of
-  // up to 16 points just before the tile and of up to 16 just after it
-  // (lanes 0-15 fetch them, two points each).
-  float nb_before, nb_after;
-  {
-    const int64_t send = A.set_start[it.set + 1];
-    float wy = -2.0f;
-    if (lane < 8) {
-      const int64_t e = it.start - 16 + 2 * lane;
-      if (e >= sstart) wy = fmaxf(A.pts[e].y, A.pts[e + 1].y);
-    } else if (lane < 16) {
-      const int64_t e = it.start + it.len + 2 * (lane - 8);
-      if (e + 1 < send) wy = fmaxf(A.pts[e].y, A.pts[e + 1].y);
-      else if (e < send) wy = A.pts[e].y;
-    }
-    // maximum over each group of 8 lanes, then read from lanes 0 and 8
-    wy = fmaxf(wy, dpp<DPP_QUAD_XOR1>(wy, wy));
-    wy = fmaxf(wy, dpp<DPP_QUAD_XOR2>(wy, wy));
-    wy = fmaxf(wy, dpp<DPP_ROW_HALF_MIRROR>(wy, wy));
-    nb_before = readlane(wy, 0);
-    nb_after = readlane(wy, 8);
-  }
-  if (it.len == 64 * K && (((uintptr_t)src) & 15u) == 0) {
+  const bool full = it.len == 64 * K && (((uintptr_t)src) & 15u) == 0;
+  if (full) {
     // full, 16-byte aligned tile (the common case): no per-element tests
     const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
 #pragma unroll
     for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
+  } else {
+    const bool al = (((uintptr_t)src) & 15u) == 0;
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
+      if (e + 1 < it.len) {
+        if (al) {
+          v[r] = *reinterpret_cast<const float4 *>(src + e);
+        } else {
+          const float2 a = src[e], b = src[e + 1];
+          v[r] = make_float4(a.x, a.y, b.x, b.y);
+        }
+      } else if (e < it.len) {
+        const float2 a = src[e];
+        v[r].x = a.x;
+        v[r].y = a.y;
+      }
+    }
+  }
+  float w0, w1;  // this lane's two witness heights (-2: none)
+  {
+    const int64_t wlo = it.start - it.nb_lo, whi = it.start + it.len + it.nb_hi;
+    const int64_t e = lane < 8 ? it.start - 16 + 2 * lane : it.start + it.len + 2 * (lane - 8);
+    const bool ok0 = lane < 16 && (lane < 8 ? e >= wlo : e < whi);
+    const bool ok1 = lane < 16 && (lane < 8 ? e + 1 >= wlo : e + 1 < whi);
+    const float y0 = A.pts[ok0 ? e : it.start].y, y1 = A.pts[ok1 ? e + 1 : it.start].y;
+    w0 = ok0 ? y0 : -2.0f;
+    w1 = ok1 ? y1 : -2.0f;
+  }
+  const float prev_x = A.pts[it.start - (it.rel0 > 0 ? 1 : 0)].x;
+  const float prev_tile_x = validate && it.rel0 > 0 ? prev_x : -1.0f;  // -1: below every valid x
+
+  int err = 0;
+  bool bad = false;  // some check failed, or the quick checks cannot vouch
+  if (full) {
     if (validate) {
       // Quick checks that can only err towards `bad`: |y| <= 1 (NaN fails
       // the grid test instead), y * 2^30 without fraction (the bits of a
@@ -337,24 +354,6 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       *d = v[r];
     }
   } else {
-    const bool al = (((uintptr_t)src) & 15u) == 0;
-#pragma unroll
-    for (int r = 0; r < NV; ++r) {
-      const int e = 2 * (lane + 64 * r);
-      v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
-      if (e + 1 < it.len) {
-        if (al) {
-          v[r] = *reinterpret_cast<const float4 *>(src + e);
-        } else {
-          const float2 a = src[e], b = src[e + 1];
-          v[r] = make_float4(a.x, a.y, b.x, b.y);
-        }
-      } else if (e < it.len) {
-        const float2 a = src[e];
-        v[r].x = a.x;
-        v[r].y = a.y;
-      }
-    }
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
@@ -365,6 +364,16 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       *reinterpret_cast<float4 *>(sxy + (e / K) * S + (e % K)) = v[r];
     }
     bad = err != 0;
+  }
+  // witness maxima: over each group of 8 lanes, then read from lanes 0 and 8
+  float nb_before, nb_after;
+  {
+    float wy = fmaxf(w0, w1);
+    wy = fmaxf(wy, dpp<DPP_QUAD_XOR1>(wy, wy));
+    wy = fmaxf(wy, dpp<DPP_QUAD_XOR2>(wy, wy));
+    wy = fmaxf(wy, dpp<DPP_ROW_HALF_MIRROR>(wy, wy));
+    nb_before = readlane(wy, 0);
+    nb_after = readlane(wy, 8);
   }
   wave_sync();
   const int my_len = min(max(it.len - lane * K, 0), K);
@@ -409,7 +418,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   const float incp = wave_prefix_max(ymax), incs = wave_suffix_max(ymax);
   const float exp_pre = fmaxf(dpp<DPP_WAVE_SHR1>(-2.0f, incp), nb_before);  // earlier strips
   const float exp_suf = fmaxf(dpp<DPP_WAVE_SHL1>(-2.0f, incs), nb_after);   // later strips
-  const int rel0 = (int)(it.start - sstart);
+  const int rel0 = it.rel0;
 
   // ---- 3. elimination; few survivors leave as a point list
   if (K == 16 && !it.final_) {
@@ -545,7 +554,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   const int hb = nleaf ? sblk[0].x : 0, hc = nleaf ? sblk[0].y : 0;
   if (it.final_) {
     if (__ballot(err != 0)) err = wave_min(err);
-    int32_t *dst = A.out_idx + sstart;
+    int32_t *dst = A.out_idx + (it.start - it.rel0);
     for (int k = lane; k < hc; k += 64) dst[k] = rel0 + (int)sid[hb + k];
     if (lane == 0) A.out_counts[it.set] = err ? err : hc;
   } else {
@@ -1047,6 +1056,9 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       it.start = set_offsets[s] + t * p->T;
       it.len = (int32_t)std::min<int64_t>(p->T, n - t * p->T);
       it.set = s;
+      it.rel0 = (int32_t)(t * p->T);
+      it.nb_lo = (int16_t)std::min<int64_t>(16, t * p->T);
+      it.nb_hi = (int16_t)std::min<int64_t>(16, n - t * p->T - it.len);
       it.final_ = nt == 1;
       it.pad = 0;
       tiles.push_back(it);
