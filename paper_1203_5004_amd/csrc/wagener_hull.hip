@@ -79,6 +79,8 @@ struct RunArgs {
   int32_t *out_counts;
   upper_hull_stats *stats;   // [S] or null
   int64_t n_total;           // points over all sets (workspace length)
+  int32_t tile_len;          // T
+  int32_t one_set;           // 1: a single set, whose tiles follow from the tile index
   uint32_t flags;
 };
 
@@ -266,7 +268,18 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
 
   const int tile = blockIdx.x;
-  const TileItem it = items[tile];
+  TileItem it;
+  if (A.one_set) {  // tile t of the only set: no item to fetch
+    it.start = (int64_t)tile * A.tile_len;
+    it.len = (int32_t)min((int64_t)A.tile_len, A.n_total - it.start);
+    it.set = 0;
+    it.rel0 = (int32_t)it.start;
+    it.nb_lo = (int16_t)min(16, it.rel0);
+    it.nb_hi = (int16_t)min((int64_t)16, A.n_total - it.start - it.len);
+    it.final_ = gridDim.x == 1;
+  } else {
+    it = items[tile];
+  }
   const int lane = threadIdx.x;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
   const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
@@ -1155,6 +1168,8 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   A.out_counts = out_counts;
   A.stats = stats;
   A.n_total = p->N;
+  A.tile_len = p->T;
+  A.one_set = p->S == 1;
   A.flags = p->flags;
   if (!(p->flags & UH_FLAG_GRAPH)) return enqueue_run(p, A, stream);
 
