@@ -260,7 +260,11 @@ __device__ __forceinline__ int wave_min(int v) {
 template <int K>
 __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
                                                   int32_t *cnt_out) {
-  constexpr int S = K + 2;
+  constexpr int S = K;       // a strip's slot in LDS: K points, no padding
+  // 16-byte chunk c of strip s sits at chunk c ^ swz(s) of the slot, so the
+  // transpose writes (8 lanes per strip) and the strip reads (one strip per
+  // lane) touch distinct LDS banks
+  auto swz = [](int strip) { return (strip ^ (strip >> 3)) & (K / 2 - 1); };
   constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
   constexpr float PAD_X = 2.0f, PAD_Y = -4.0f;  // right of / below every valid point
   __shared__ __attribute__((aligned(16))) float2 sxy[64 * S];
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
       float4 *d = reinterpret_cast<float4 *>(
-          __builtin_assume_aligned(sxy + (e / K) * S + (e % K), 16));
+          __builtin_assume_aligned(sxy + (e / K) * S + 2 * (((e % K) >> 1) ^ swz(e / K)), 16));
       *d = v[r];
     }
   } else {
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
         if (e < it.len) err = min(err, check_point(make_float2(v[r].x, v[r].y)));
         if (e + 1 < it.len) err = min(err, check_point(make_float2(v[r].z, v[r].w)));
       }
-      *reinterpret_cast<float4 *>(sxy + (e / K) * S + (e % K)) = v[r];
+      *reinterpret_cast<float4 *>(sxy + (e / K) * S + 2 * (((e % K) >> 1) ^ swz(e / K))) = v[r];
     }
     bad = err != 0;
   }
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   float2 p[K];
 #pragma unroll
   for (int k = 0; k < K / 2; ++k) {
-    const float4 q = *reinterpret_cast<const float4 *>(st + 2 * k);
+    const float4 q = *reinterpret_cast<const float4 *>(st + 2 * (k ^ swz(lane)));
     p[2 * k] = make_float2(q.x, q.y);
     p[2 * k + 1] = make_float2(q.z, q.w);
   }
@@ -461,7 +465,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
           }
           const int L = row == 0 ? Ls[0] : row == 1 ? Ls[1] : row == 2 ? Ls[2] : Ls[3];
           const int Lc = L < 0 ? 0 : L;
-          const float2 q = sxy[Lc * S + i];
+          const float2 q = sxy[Lc * S + 2 * ((i >> 1) ^ swz(Lc)) + (i & 1)];
           const float2 w = reinterpret_cast<const float2 *>(sblk)[Lc];
           const float before = fmaxf(w.x, dpp<DPP_ROW_SHR + 1>(-2.0f, row_prefix_max(q.y, -2.0f)));
           const float after = fmaxf(w.y, dpp<DPP_ROW_SHL + 1>(-2.0f, row_suffix_max(q.y, -2.0f)));
@@ -528,15 +532,15 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   // ---- 4. strip hoods, then rounds of Wagener merges over them
   int nleaf;
   {
-    // the serial strip hood over each strip's survivors (re-read from LDS;
-    // the stack overwrites the slot from its start, never past a survivor
-    // still to be read); the non-empty strip hoods are the leaves
+    // the serial strip hood over each strip's survivors, taken from the
+    // registers in order; its stack overwrites the strip's LDS slot from
+    // the start (in plain order); the non-empty strip hoods are the leaves
     int cnt = 0;
     float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
-    while (keep) {
-      const int i = __builtin_ctz(keep);
-      keep &= keep - 1;
-      const float2 r = st[i];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (!((keep >> i) & 1u)) continue;
+      const float2 r = p[i];
       if (cnt >= 1 && r.x == t1.x) {
         if (r.y <= t1.y) continue;  // the top hides r (ties: lower index)
         --cnt;                      // r hides the top
