@@ -33,17 +33,23 @@ def log(*a):
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources' code (comments and whitespace removed), so
+    that a counter summary stays attached to the code it was measured on."""
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str, strip: int):
     """HBM bytes per tile-kernel launch from the committed rocprofv3 --pmc
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"tile_kernel_{workload.replace('^', 'p')}_pmc.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -82,7 +88,7 @@ def cpu_baseline(pts_np, off, budget_s: float):
     import oracle
     t_total, reps = 0.0, 0
     out = cnt = None
-    while reps < 1 or (t_total < budget_s and reps < 5):
+    while reps < 1 or t_total < budget_s:
         t0 = time.perf_counter()
         out, cnt = oracle.upper_hull_batched(pts_np, off)
         t_total += time.perf_counter() - t0
@@ -98,6 +104,8 @@ def main():
     ap.add_argument("--workload", default="uniform_2^27")
     ap.add_argument("--strip", type=int, default=16)
     ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
+    ap.add_argument("--force-fallback", action="store_true",
+                    help="predicate ablation: every orientation test takes the exact FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--compare-plain", action="store_true",
@@ -138,7 +146,8 @@ def main():
         log("[bench] calibration copy: 2 x 1 GiB device-to-device")
     pts = torch.from_numpy(pts_np).to(dev)
     N, S = len(pts_np), len(off) - 1
-    flags = uh.UH_FLAG_GRAPH if args.graph else 0
+    flags = (uh.UH_FLAG_GRAPH if args.graph else 0) | \
+        (uh.UH_FLAG_FORCE_FALLBACK if args.force_fallback else 0)
     plan = uh.upper_hull_plan_create(off, strip=args.strip, flags=flags)
     out_idx = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
     out_cnt = torch.empty(S, dtype=torch.int32, device=dev)
@@ -247,7 +256,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_points": N, "sets": S, "strip": args.strip,
                    "tile_points": 64 * args.strip, "launches_per_step": plan.launches,
-                   "graph": bool(args.graph), "corners": h_total,
+                   "graph": bool(args.graph), "force_fallback": bool(args.force_fallback),
+                   "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),
                    "fallback_rate": (fallbacks / evals) if evals else 0.0,
                    "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),

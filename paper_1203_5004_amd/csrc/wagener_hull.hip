@@ -7,15 +7,18 @@
 // device-resident, in three kinds of launch enqueued back to back:
 //
 //   init_kernel   clears per-set status and counters.
-//   tile_kernel   one workgroup per tile of T = 256 * K points of one set:
-//                 coalesced load (plus contract checks) into LDS; each lane
-//                 builds the hood of its strip of K consecutive points
-//                 serially (the first step of the paper's work-optimal
-//                 variant in its conclusions); then log2(256) = 8 rounds of
-//                 Wagener merges of adjacent strip hoods in LDS, each merge
-//                 finding its bridge with the sampled search of one wave and
-//                 compacting P[0..a] ++ Q[b..]; the tile hood goes to the
-//                 workspace (or straight to the output for a one-tile set).
+//   tile_kernel   one wave per tile of T = 64 * K points of one set:
+//                 coalesced load with the contract checks, strips of K
+//                 consecutive points per lane, an exact elimination of
+//                 points that cannot be corners; few survivors leave as a
+//                 sorted point list, otherwise each lane builds the hood of
+//                 its strip serially (the first step of the paper's
+//                 work-optimal variant in its conclusions) and up to six
+//                 rounds of Wagener merges of adjacent strip hoods run in
+//                 LDS, each merge finding its bridge with the lanes of the
+//                 wave and compacting P[0..a] ++ Q[b..]; the tile's result
+//                 goes to the workspace (or straight to the output for a
+//                 one-tile set).
 //   merge_kernel  one workgroup merges up to F consecutive hoods of the
 //                 previous level of one set through log2(F) further rounds,
 //                 in LDS when they fit, else in place in the workspace.
