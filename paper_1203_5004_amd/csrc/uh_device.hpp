@@ -330,8 +330,17 @@ __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
       if (r < npair) {
         i = (int)(((float)r + 0.5f) * rq);
         j = r - i * hq;
-        hit = g_classify(xy[bp + i], xy + bq, j, hq, oc, fe) == EQUAL &&
-              f_classify(xy[bq + j], xy + bp, i, hp, oc, fe) == EQUAL;
+        // g(P[i], Q[j]) and f(Q[j], P[i]) as in g_classify / f_classify,
+        // with the six corners read at once and all four tests evaluated
+        const int im = i > 0 ? i - 1 : 0, ip = i + 1 < hp ? i + 1 : i;
+        const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < hq ? j + 1 : j;
+        const float2 pi = xy[bp + i], pp = xy[bp + im], pn = xy[bp + ip];
+        const float2 qj = xy[bq + j], qp = xy[bq + jm], qn = xy[bq + jp];
+        const int gl = orient_sign(pi, qj, qn, oc, fe), gh = orient_sign(pi, qj, qp, oc, fe);
+        const int fl = orient_sign(pi, qj, pn, oc, fe), fh = orient_sign(pi, qj, pp, oc, fe);
+        const bool g_eq = !(j + 1 < hq && gl >= 0) && !(j > 0 && gh > 0);
+        const bool f_eq = !(i + 1 < hp && fl > 0) && !(i > 0 && fh >= 0);
+        hit = g_eq && f_eq;
       }
       const uint64_t m = (__ballot(hit) >> gbase) & gmask;
       if (m) {

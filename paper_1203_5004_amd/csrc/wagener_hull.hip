@@ -209,6 +209,25 @@ __device__ __forceinline__ float wave_suffix_max(float v, float id = -2.0f) {
   return fmaxf(v, row == 0 ? t123 : row == 1 ? t23 : row == 2 ? t3 : id);
 }
 
+// Exclusive max over the lanes of this lane's segment of W lanes (W = 16:
+// one row; W = 32: two rows) below it (pre) and above it (post).
+template <int W>
+__device__ __forceinline__ void segment_excl_max(float v, float id, float &pre, float &post) {
+  const int lane = threadIdx.x & 63;
+  float a = row_prefix_max(v, id), b = row_suffix_max(v, id);
+  if constexpr (W == 16) {
+    pre = dpp<DPP_ROW_SHR + 1>(id, a);
+    post = dpp<DPP_ROW_SHL + 1>(id, b);
+  } else {
+    a = fmaxf(a, dpp<DPP_ROW_BCAST15, 0xa>(id, a));  // rows 1, 3 take rows 0, 2
+    const float t1 = readlane(b, 16), t3 = readlane(b, 48);
+    const int row = lane >> 4;
+    b = fmaxf(b, row == 0 ? t1 : row == 2 ? t3 : id);
+    pre = (lane & 31) == 0 ? id : dpp<DPP_WAVE_SHR1>(id, a);
+    post = (lane & 31) == 31 ? id : dpp<DPP_WAVE_SHL1>(id, b);
+  }
+}
+
 // Number of set bits of m in the lanes below this one.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -441,16 +460,17 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
   const int rel0 = it.rel0;
 
   // ---- 3. elimination; few survivors leave as a point list
-  if (K == 16 && !it.final_) {
+  if ((K == 16 || K == 32) && !it.final_) {
+    constexpr int SPP = 64 / K;  // candidate strips per pass
     const uint64_t cand = __ballot(ymax > exp_pre || ymax >= exp_suf);
     const int ncand = __builtin_popcountll(cand);
-    if (ncand <= 16) {
-      // each row of 16 lanes takes one candidate strip per pass; lane i of
-      // the row tests point i against the exact earlier / later maxima
+    if (ncand <= 4 * SPP) {
+      // each segment of K lanes takes one candidate strip per pass; lane i of
+      // the segment tests point i against the exact earlier / later maxima
       reinterpret_cast<float2 *>(sblk)[lane] = make_float2(exp_pre, exp_suf);
       wave_sync();
-      const int row = lane >> 4, i = lane & 15;
-      const int npass = (ncand + 3) >> 2;
+      const int seg = lane / K, i = lane % K;
+      const int npass = (ncand + SPP - 1) / SPP;
       uint64_t rest = cand, kb[4];
       float2 kp[4];
       int kid[4], nsurv = 0;
@@ -460,18 +480,22 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
         kp[ps] = make_float2(0.f, 0.f);
         kid[ps] = 0;
         if (ps < npass) {
-          int Ls[4];
+          int Ls[SPP];
 #pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
+          for (int rr = 0; rr < SPP; ++rr) {
             Ls[rr] = rest ? (int)__builtin_ctzll(rest) : -1;
             rest &= rest - 1;
           }
-          const int L = row == 0 ? Ls[0] : row == 1 ? Ls[1] : row == 2 ? Ls[2] : Ls[3];
+          int L = Ls[0];
+#pragma unroll
+          for (int rr = 1; rr < SPP; ++rr) L = seg == rr ? Ls[rr] : L;
           const int Lc = L < 0 ? 0 : L;
           const float2 q = sxy[Lc * S + 2 * ((i >> 1) ^ swz(Lc)) + (i & 1)];
           const float2 w = reinterpret_cast<const float2 *>(sblk)[Lc];
-          const float before = fmaxf(w.x, dpp<DPP_ROW_SHR + 1>(-2.0f, row_prefix_max(q.y, -2.0f)));
-          const float after = fmaxf(w.y, dpp<DPP_ROW_SHL + 1>(-2.0f, row_suffix_max(q.y, -2.0f)));
+          float in_pre, in_post;
+          segment_excl_max<K == 32 ? 32 : 16>(q.y, -2.0f, in_pre, in_post);
+          const float before = fmaxf(w.x, in_pre);
+          const float after = fmaxf(w.y, in_post);
           const bool keep = L >= 0 && (q.y > before || q.y >= after);
           kb[ps] = __ballot(keep);
           kp[ps] = q;
@@ -506,7 +530,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       bm = fmaxf(bm, p[i].y);
     }
   }
-  if constexpr (K != 16) {
+  if constexpr (K != 16 && K != 32) {
     // survivor list for the other strip widths: ranks by a wave prefix sum
     const int nk = __builtin_popcount(keep);
     int koff = nk;
