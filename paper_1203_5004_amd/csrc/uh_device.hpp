@@ -336,10 +336,12 @@ __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
         const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < hq ? j + 1 : j;
         const float2 pi = xy[bp + i], pp = xy[bp + im], pn = xy[bp + ip];
         const float2 qj = xy[bq + j], qp = xy[bq + jm], qn = xy[bq + jp];
-        const int gl = orient_sign(pi, qj, qn, oc, fe), gh = orient_sign(pi, qj, qp, oc, fe);
-        const int fl = orient_sign(pi, qj, pn, oc, fe), fh = orient_sign(pi, qj, pp, oc, fe);
-        const bool g_eq = !(j + 1 < hq && gl >= 0) && !(j > 0 && gh > 0);
-        const bool f_eq = !(i + 1 < hp && fl > 0) && !(i > 0 && fh >= 0);
+        // (a missing neighbour takes no test: it would compare a corner with
+        // itself, an exact zero that the filter cannot certify)
+        const bool g_eq = !(j + 1 < hq && orient_sign(pi, qj, qn, oc, fe) >= 0) &&
+                          !(j > 0 && orient_sign(pi, qj, qp, oc, fe) > 0);
+        const bool f_eq = !(i + 1 < hp && orient_sign(pi, qj, pn, oc, fe) > 0) &&
+                          !(i > 0 && orient_sign(pi, qj, pp, oc, fe) >= 0);
         hit = g_eq && f_eq;
       }
       const uint64_t m = (__ballot(hit) >> gbase) & gmask;

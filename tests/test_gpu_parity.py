@@ -198,6 +198,20 @@ def test_force_fallback_identical_and_stats():
     assert np.array_equal(st1[:, 1], st1[:, 0])  # forced: every test falls back
 
 
+def test_exact_path_rare_in_general_position():
+    # Uniform sets on a fine grid have almost no ambiguous orientation
+    # tests: the FP32 filter must decide nearly all of them (no test of a
+    # corner against itself, which is an exact zero the filter cannot
+    # certify, may reach the exact path).
+    sets = [synth.uniform(200000, 22, seed=s) for s in range(4)]
+    sets += [synth.uniform(3000, 22, seed=9)]
+    pts, off = synth.concat_sets(sets)
+    out, cnt, st = gpu_batched(pts, off, with_stats=True)
+    assert_batched_equal(pts, off, out, cnt)
+    evals, fb = int(st[:, 0].sum()), int(st[:, 1].sum())
+    assert evals > 0 and fb <= 0.01 * evals, (evals, fb)
+
+
 def test_determinism_repeated_runs():
     xy = synth.arc(300000, 20, 4, seed=12)
     c0, i0 = gpu_hull(xy)
