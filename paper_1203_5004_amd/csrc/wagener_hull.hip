@@ -45,8 +45,10 @@
 
 namespace uh {
 
-constexpr int BLOCK = 256;       // threads per workgroup (4 waves)
+constexpr int BLOCK = 256;       // threads per merge workgroup (4 waves)
+constexpr int WIDE = 512;        // threads of the last merge of a set with 257 .. 512 children
 constexpr int VMAX = 6144;       // corners a merge workgroup keeps in LDS (two per CU)
+constexpr int VMAX_WIDE = 12000; // ... and the wide one (one per CU)
 // Bit 31 of a tile's output count: the tile wrote its surviving points (a
 // sorted point list, not yet a hood); the merge kernel makes it a hood.
 constexpr uint32_t POINTS_FLAG = 0x80000000u;
@@ -614,6 +616,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
 
 // ---------------------------------------------------------------- merges
 // Exclusive prefix sum of one value per thread over the workgroup.
+template <int BLK>
 __device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int x = v;
@@ -625,29 +628,30 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &tota
   __syncthreads();
   int before = 0;
   total = 0;
-  for (int k = 0; k < BLOCK / 64; ++k) {
+  for (int k = 0; k < BLK / 64; ++k) {
     if (k < w) before += swave[k];
     total += swave[k];
   }
   return before + x - v;
 }
 
-// One workgroup merges the hoods of up to F = 256 consecutive blocks of the
-// previous level of one set (log2 F more rounds).  When their corners fit
+// One workgroup of BLK threads merges the hoods of up to BLK consecutive
+// blocks of the previous level of one set (log2 BLK more rounds).  When their corners fit
 // in LDS: gather them back to back, six rounds inside each wave (64
 // children -> 1), then wave 0 merges the four wave hoods.  Otherwise the
 // same rounds run in place in the workspace (global memory), each merge by
 // a group of lanes with workgroup barriers between the reads and writes of
 // the compaction.
-__global__ __launch_bounds__(BLOCK) void merge_kernel(
+template <int BLK, int VMX>
+__global__ __launch_bounds__(BLK) void merge_kernel(
     RunArgs A, const MergeItem *items, const int32_t *child_cnt, int32_t *cnt_out) {
-  __shared__ float2 bxy[VMAX];
-  __shared__ int32_t bid[VMAX];
-  __shared__ int bcnt[BLOCK];
-  __shared__ int soff[BLOCK];
-  __shared__ int2 sblk[BLOCK];  // LDS path: (base, count) per child block
-  __shared__ int2 sres[BLOCK / 2];
-  __shared__ int swave[BLOCK / 64 + 1];
+  __shared__ float2 bxy[VMX];
+  __shared__ int32_t bid[VMX];
+  __shared__ int bcnt[BLK];
+  __shared__ int soff[BLK];
+  __shared__ int2 sblk[BLK];  // LDS path: (base, count) per child block
+  __shared__ int2 sres[BLK / 2];
+  __shared__ int swave[BLK / 64 + 1];
   __shared__ int smax;
 
   const MergeItem it = items[blockIdx.x];
@@ -682,7 +686,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   const bool pts = (craw & POINTS_FLAG) != 0;
   const int c = (int)(craw & ~POINTS_FLAG);
   int V;
-  const int o = block_exclusive_scan(c, swave, V);
+  const int o = block_exclusive_scan<BLK>(c, swave, V);
   bcnt[tid] = c;
   soff[tid] = o;
   int npow = 1;
@@ -690,7 +694,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   OrientCount oc;
   __syncthreads();
 
-  if (V <= VMAX) {
+  if (V <= VMX) {
     // ---- gather: the prefetched entries to their places, then thread k
     // copies whatever child k has beyond them, eight loads in flight
 #pragma unroll
@@ -738,14 +742,14 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
         for (int u = 0; u < 8; ++u) cmax = fmaxf(cmax, yv[u]);
       }
       const float incp = wave_prefix_max(cmax), incs = wave_suffix_max(cmax);
-      __shared__ float swp[BLOCK / 64], sws[BLOCK / 64];
+      __shared__ float swp[BLK / 64], sws[BLK / 64];
       if (lane == 63) swp[w] = incp;
       if (lane == 0) sws[w] = incs;
       float pre = __shfl_up(incp, 1, 64), suf = __shfl_down(incs, 1, 64);
       if (lane == 0) pre = -2.0f;
       if (lane == 63) suf = -2.0f;
       __syncthreads();
-      for (int k = 0; k < BLOCK / 64; ++k) {
+      for (int k = 0; k < BLK / 64; ++k) {
         if (k < w) pre = fmaxf(pre, swp[k]);
         if (k > w) suf = fmaxf(suf, sws[k]);
       }
@@ -781,7 +785,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
       if (lane == 0) swave[w] = __builtin_popcountll(ne);
       __syncthreads();
       int before = 0, total = 0;
-      for (int k = 0; k < BLOCK / 64; ++k) {
+      for (int k = 0; k < BLK / 64; ++k) {
         before += k < w ? swave[k] : 0;
         total += swave[k];
       }
@@ -792,10 +796,10 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
         if (kept > 0)
           sblk[(w << 6) + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
       }
-      if (tid == 0) swave[BLOCK / 64] = total;
+      if (tid == 0) swave[BLK / 64] = total;
     }
     __syncthreads();
-    const int total_leaves = swave[BLOCK / 64];
+    const int total_leaves = swave[BLK / 64];
     if (total_leaves > 64) wave_rounds(bxy, bid, sblk + (w << 6), swave[w], oc, fe);
     __syncthreads();
     if (w == 0) {
@@ -808,7 +812,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
         // the wave hoods (one per wave that had leaves), left to right
         int nb0 = 0, nc0 = 0;
         bool have = false;
-        for (int k = 0; k < BLOCK / 64; ++k) {
+        for (int k = 0; k < BLK / 64; ++k) {
           if (swave[k] == 0) continue;
           const int2 Q = sblk[k << 6];
           if (!have) {
@@ -853,7 +857,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
 #pragma unroll 1
   for (int j = 0; (1 << j) < nch; ++j) {
     const int M = npow >> (j + 1);
-    const int G = BLOCK / M;
+    const int G = BLK / M;
     const int m = tid / G, t = tid % G;
     const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
     int a = -1, b = 0, hp = 0, hqe = 0, qs = 0;
@@ -916,7 +920,7 @@ __global__ __launch_bounds__(BLOCK) void merge_kernel(
   const int32_t *res_id = A.ws_idx + it.off;
   if (it.final_) {
     int32_t *dst = A.out_idx + A.set_start[it.set];
-    for (int k = tid; k < hc; k += BLOCK) dst[k] = res_id[k];
+    for (int k = tid; k < hc; k += BLK) dst[k] = res_id[k];
     if (tid == 0) {
       const int st = A.set_status[it.set];
       A.out_counts[it.set] = st ? st : hc;
@@ -963,6 +967,7 @@ struct upper_hull_plan {
   uint32_t flags = 0;
   int32_t ntiles = 0;
   std::vector<int32_t> pass_items;  // merge items per pass
+  std::vector<char> pass_wide;      // per pass: some item has more than BLOCK children
   // device memory
   int64_t *d_set_start = nullptr;
   TileItem *d_tiles = nullptr;
@@ -1031,8 +1036,12 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
   }
   for (size_t ps = 0; ps < p->pass_items.size(); ++ps) {
     const int32_t *ccnt = ps == 0 ? p->d_cnt0 : p->d_cnt[ps - 1];
-    hipLaunchKernelGGL(merge_kernel, dim3(p->pass_items[ps]), dim3(BLOCK), 0, stream, A,
-                       p->d_items[ps], ccnt, p->d_cnt[ps]);
+    if (p->pass_wide[ps])
+      hipLaunchKernelGGL((merge_kernel<WIDE, VMAX_WIDE>), dim3(p->pass_items[ps]), dim3(WIDE), 0,
+                         stream, A, p->d_items[ps], ccnt, p->d_cnt[ps]);
+    else
+      hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), dim3(p->pass_items[ps]), dim3(BLOCK), 0,
+                         stream, A, p->d_items[ps], ccnt, p->d_cnt[ps]);
   }
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
@@ -1116,16 +1125,22 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   for (;;) {
     std::vector<MergeItem> items;
     std::vector<int32_t> nfirst(num_sets), ncount(num_sets);
+    // With the default fan-in, a set with BLOCK + 1 .. WIDE blocks left can
+    // finish in one wide workgroup (one per CU), if few sets need one.
+    int32_t nwide = 0;
+    for (int32_t s = 0; s < num_sets; ++s) nwide += F == BLOCK && count[s] > BLOCK && count[s] <= WIDE;
+    const bool use_wide = nwide > 0 && nwide <= 256;
     for (int32_t s = 0; s < num_sets; ++s) {
       nfirst[s] = (int32_t)items.size();
       ncount[s] = 0;
       if (count[s] <= 1) continue;
-      const int32_t nitems = (count[s] + F - 1) / F;
+      const int32_t FS = use_wide && F == BLOCK && count[s] <= WIDE ? WIDE : F;
+      const int32_t nitems = (count[s] + FS - 1) / FS;
       for (int32_t i = 0; i < nitems; ++i) {
         MergeItem m;
-        m.child0 = first[s] + i * F;
-        m.nch = std::min(F, count[s] - i * F);
-        m.off = set_offsets[s] + (int64_t)i * F * stride;
+        m.child0 = first[s] + i * FS;
+        m.nch = std::min(FS, count[s] - i * FS);
+        m.off = set_offsets[s] + (int64_t)i * FS * stride;
         m.stride = stride;
         m.set = s;
         m.final_ = nitems == 1;
@@ -1158,6 +1173,9 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     p->d_items.push_back(di);
     p->d_cnt.push_back(dcnt);
     p->pass_items.push_back((int32_t)items.size());
+    bool wide = false;
+    for (const MergeItem &m : items) wide = wide || m.nch > BLOCK;
+    p->pass_wide.push_back(wide);
   }
   rc = rc ? rc : dalloc(&p->ws_xy, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws_idx, (size_t)p->N);
