@@ -79,6 +79,8 @@ struct RunArgs {
   const int64_t *set_start;  // [S + 1]
   float2 *ws_xy;             // [N] corner coordinates at their slots
   int32_t *ws_idx;           // [N] set-relative index of each corner
+  float2 *ws2_xy;            // [N] second workspace: the global merge path
+  int32_t *ws2_idx;          //     alternates between the two
   int32_t *set_status;       // [S] worst data error seen (0 = none)
   int32_t *out_idx;
   int32_t *out_counts;
@@ -652,7 +654,6 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   __shared__ int2 sblk[BLK];  // LDS path: (base, count) per child block
   __shared__ int2 sres[BLK / 2];
   __shared__ int swave[BLK / 64 + 1];
-  __shared__ int smax;
 
   const MergeItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
@@ -850,27 +851,28 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     return;
   }
 
-  // ---- too large for LDS: the same rounds in place in the workspace
+  // ---- too large for LDS: the same rounds in the workspace, each round
+  // copying the merged hoods into the other workspace (no copy overlaps its
+  // source, so every thread copies its share with many loads in flight)
   if (pts && c > 0)  // point-list children first become hoods, in place
     bcnt[tid] = chain_inplace(A.ws_xy + g, A.ws_idx + g, c, oc, fe);
   __syncthreads();
+  int flip = 0;  // 0: the blocks are in ws, 1: in ws2
 #pragma unroll 1
   for (int j = 0; (1 << j) < nch; ++j) {
     const int M = npow >> (j + 1);
     const int G = BLK / M;
     const int m = tid / G, t = tid % G;
     const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
-    int a = -1, b = 0, hp = 0, hqe = 0, qs = 0;
-    float2 *P = nullptr, *Q = nullptr;
-    int32_t *Pid = nullptr, *Qid = nullptr;
-    if (tid == 0) smax = 0;
-    if (lp < nch && lq < nch) {
-      const int64_t op = it.off + lp * it.stride, oq = it.off + lq * it.stride;
-      P = A.ws_xy + op;
-      Q = A.ws_xy + oq;
-      Pid = A.ws_idx + op;
-      Qid = A.ws_idx + oq;
-      hp = bcnt[lp];
+    const float2 *Sxy = flip ? A.ws2_xy : A.ws_xy;
+    const int32_t *Sid = flip ? A.ws2_idx : A.ws_idx;
+    float2 *Dxy = flip ? A.ws_xy : A.ws2_xy;
+    int32_t *Did = flip ? A.ws_idx : A.ws2_idx;
+    const bool has_p = lp < nch, active = lp < nch && lq < nch;
+    const int64_t op = it.off + lp * it.stride, oq = it.off + lq * it.stride;
+    int a = -1, b = 0, hp = has_p ? bcnt[lp] : 0, hqe = 0, qs = 0;
+    if (active) {
+      const float2 *P = Sxy + op, *Q = Sxy + oq;
       const int hq = bcnt[lq];
       if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
       hqe = hq - qs;
@@ -880,7 +882,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t, a, b, oc,
                                       fe);
     }
-    __syncthreads();  // smax cleared, and searches done reading
+    __syncthreads();  // searches done
     if (G > 64) {
       if (t == 0) sres[m] = make_int2(a, b);
       __syncthreads();
@@ -888,36 +890,62 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       a = rr.x;
       b = rr.y;
     }
-    const bool active = lp < nch && lq < nch;
-    const int nsurv = active ? hqe - b : 0;
-    const int chunks = (nsurv + G - 1) / G;
-    if (t == 0 && active) atomicMax(&smax, chunks);
-    __syncthreads();
-    const int maxchunks = smax;
-    // left shift Q[b..] to P[a+1..]: destination never passes the source,
-    // so reading chunk c before anyone writes it keeps every value intact
-    for (int ch = 0; ch < maxchunks; ++ch) {
-      const int e = ch * G + t;
-      float2 v = make_float2(0.f, 0.f);
-      int32_t vi = 0;
-      const bool mine = e < nsurv;
-      if (mine) {
-        v = Q[qs + b + e];
-        vi = Qid[qs + b + e];
+    // P[0..a] ++ Q[qs + b ..] to the other workspace at P's slot; a block
+    // without a partner this round is copied whole
+    const int np = active ? a + 1 : hp;
+    const int nq = active ? hqe - b : 0;
+    const int64_t qsrc = oq + qs + b - np;  // source of merged entry e >= np
+    for (int e0 = 0; e0 < np + nq; e0 += 8 * G) {
+      float2 vx[8];
+      int32_t vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * G + t;
+        if (e < np + nq) {
+          const int64_t src = e < np ? op + e : qsrc + e;
+          vx[u] = Sxy[src];
+          vi[u] = Sid[src];
+        }
       }
-      __syncthreads();
-      if (mine) {
-        P[a + 1 + e] = v;
-        Pid[a + 1 + e] = vi;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * G + t;
+        if (e < np + nq) {
+          Dxy[op + e] = vx[u];
+          Did[op + e] = vi[u];
+        }
       }
-      __syncthreads();
     }
-    if (t == 0 && active) bcnt[lp] = a + 1 + nsurv;
+    __syncthreads();  // every lane has read bcnt
+    if (t == 0 && has_p) bcnt[lp] = np + nq;
+    flip ^= 1;
     __syncthreads();
   }
+  if (flip && !it.final_) {  // the result back to ws, where the next level reads it
+    const int hc = bcnt[0];
+    for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {
+      float2 vx[8];
+      int32_t vi[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * BLK + tid;
+        if (e < hc) {
+          vx[u] = A.ws2_xy[it.off + e];
+          vi[u] = A.ws2_idx[it.off + e];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * BLK + tid;
+        if (e < hc) {
+          A.ws_xy[it.off + e] = vx[u];
+          A.ws_idx[it.off + e] = vi[u];
+        }
+      }
+    }
+  }
   const int hc = bcnt[0];
-  const float2 *res_xy = A.ws_xy + it.off;
-  const int32_t *res_id = A.ws_idx + it.off;
+  const int32_t *res_id = (flip ? A.ws2_idx : A.ws_idx) + it.off;
   if (it.final_) {
     int32_t *dst = A.out_idx + A.set_start[it.set];
     for (int k = tid; k < hc; k += BLK) dst[k] = res_id[k];
@@ -926,7 +954,6 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       A.out_counts[it.set] = st ? st : hc;
     }
   } else {
-    (void)res_xy;
     if (tid == 0) cnt_out[blockIdx.x] = hc;
   }
   flush_wave_stats(A, it.set, oc);
@@ -974,8 +1001,8 @@ struct upper_hull_plan {
   int32_t *d_cnt0 = nullptr;
   std::vector<MergeItem *> d_items;
   std::vector<int32_t *> d_cnt;   // per pass: item corner counts
-  float2 *ws_xy = nullptr;
-  int32_t *ws_idx = nullptr;
+  float2 *ws_xy = nullptr, *ws2_xy = nullptr;
+  int32_t *ws_idx = nullptr, *ws2_idx = nullptr;
   int32_t *set_status = nullptr;
   // graph cache: (points, out_idx, out_counts, stats) -> exec
   std::map<std::tuple<const void *, void *, void *, void *>, hipGraphExec_t> graphs;
@@ -1010,6 +1037,8 @@ void free_plan_memory(upper_hull_plan *p) {
   for (auto *q : p->d_cnt) hipFree(q);
   hipFree(p->ws_xy);
   hipFree(p->ws_idx);
+  hipFree(p->ws2_xy);
+  hipFree(p->ws2_idx);
   hipFree(p->set_status);
   for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
@@ -1179,6 +1208,8 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   }
   rc = rc ? rc : dalloc(&p->ws_xy, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws_idx, (size_t)p->N);
+  rc = rc ? rc : dalloc(&p->ws2_xy, (size_t)p->N);
+  rc = rc ? rc : dalloc(&p->ws2_idx, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->set_status, (size_t)num_sets);
   if (rc) {
     free_plan_memory(p);
@@ -1212,6 +1243,8 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   A.set_start = p->d_set_start;
   A.ws_xy = p->ws_xy;
   A.ws_idx = p->ws_idx;
+  A.ws2_xy = p->ws2_xy;
+  A.ws2_idx = p->ws2_idx;
   A.set_status = p->set_status;
   A.out_idx = out_idx;
   A.out_counts = out_counts;
