@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
     ap.add_argument("--force-fallback", action="store_true",
                     help="predicate ablation: every orientation test takes the exact FP64 path")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose strip and fan-in by the library's autotuner on this workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--compare-plain", action="store_true",
@@ -148,7 +150,16 @@ def main():
     N, S = len(pts_np), len(off) - 1
     flags = (uh.UH_FLAG_GRAPH if args.graph else 0) | \
         (uh.UH_FLAG_FORCE_FALLBACK if args.force_fallback else 0)
-    plan = uh.upper_hull_plan_create(off, strip=args.strip, flags=flags)
+    fan_in = 0
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        cfg, tms = uh.upper_hull_autotune(pts, off, flags=flags & ~uh.UH_FLAG_GRAPH, reps=3)
+        args.strip, fan_in = cfg["strip"], cfg["fan_in"]
+        tuned = {"strip": args.strip, "fan_in": fan_in, "ms": round(tms, 4),
+                 "seconds": round(time.perf_counter() - t0, 1)}
+        log(f"[bench] autotune: strip {args.strip}, fan-in {fan_in} ({tms:.3f} ms)")
+    plan = uh.upper_hull_plan_create(off, strip=args.strip, fan_in=fan_in, flags=flags)
     out_idx = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
     out_cnt = torch.empty(S, dtype=torch.int32, device=dev)
     stats = torch.zeros((S, 2), dtype=torch.int64, device=dev)
@@ -256,6 +267,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_points": N, "sets": S, "strip": args.strip,
                    "tile_points": 64 * args.strip, "launches_per_step": plan.launches,
+                   "fan_in": fan_in or 256, "autotuned": tuned,
                    "graph": bool(args.graph), "force_fallback": bool(args.force_fallback),
                    "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),

@@ -158,6 +158,29 @@ int upper_hull_plan_launches(const upper_hull_plan *plan);
 int upper_hull_plan_set_probe(upper_hull_plan *plan, hipEvent_t before,
                               hipEvent_t after);
 
+/*
+ * Autotuner: chooses the tile size (T = 64 * strip points) and the number of
+ * merge rounds fused per workgroup (log2 fan_in) for a set layout by timing
+ * them on the caller's data.  Every (strip, fan_in) pair with strip in
+ * {8, 16, 32} and fan_in in {16, 64, 256} runs `reps` times (after one
+ * untimed run) on `stream` under `flags` (UH_FLAG_GRAPH is ignored); the
+ * fastest mean time wins, ties to the earlier pair.  Synchronous: returns
+ * when the timing is done.
+ *   points, set_offsets, num_sets   as for a plan (points on the device,
+ *                                    set_offsets on the host).
+ *   flags     UH_FLAG_* bits to tune under; copied into *best.
+ *   reps      1 .. 1000 timed runs per pair.
+ *   best      receives the chosen config.
+ *   best_ms   NULL, or receives its mean run time in milliseconds.
+ * A data error in the sample (a negative count) does not stop the timing.
+ * Builds a plan per pair and scratch output buffers while it runs and frees
+ * them before returning: not for use while `stream` is capturing.
+ */
+int upper_hull_autotune(const float *points, const int64_t *set_offsets,
+                        int32_t num_sets, uint32_t flags, int32_t reps,
+                        upper_hull_config *best, float *best_ms,
+                        hipStream_t stream);
+
 /* ------------------------------------------------------- building blocks */
 /*
  * The bridge of two hoods (match-and-merge, steps mam1-mam5 of the paper,

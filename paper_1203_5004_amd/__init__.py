@@ -36,7 +36,7 @@ UH_FLAG_GRAPH = 4
 EXPORTS = (
     "upper_hull_status_string", "upper_hull", "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
-    "upper_hull_plan_set_probe",
+    "upper_hull_plan_set_probe", "upper_hull_autotune",
     "upper_hull_bridge", "upper_hull_orient",
 )
 
@@ -78,6 +78,8 @@ def load_library():
     lib.upper_hull_plan_launches.restype = ctypes.c_int
     lib.upper_hull_plan_set_probe.argtypes = [p, p, p]
     lib.upper_hull_plan_set_probe.restype = ctypes.c_int
+    lib.upper_hull_autotune.argtypes = [p, p, i32, ctypes.c_uint32, i32, p, p, p]
+    lib.upper_hull_autotune.restype = ctypes.c_int
     lib.upper_hull_bridge.argtypes = [p, i32, p, i32, i32, p, p]
     lib.upper_hull_bridge.restype = ctypes.c_int
     lib.upper_hull_orient.argtypes = [p, p, p, i64, p, p, i32, p]
@@ -197,6 +199,22 @@ class Plan:
 
 def upper_hull_plan_create(set_offsets, strip=0, fan_in=0, flags=0) -> Plan:
     return Plan(set_offsets, strip, fan_in, flags)
+
+
+def upper_hull_autotune(points, set_offsets, flags=0, reps=3, stream=None):
+    """Time the candidate (strip, fan_in) pairs on `points` (cuda float32
+    [N, 2]) for this set layout; returns (config dict, mean ms per run)."""
+    torch = _torch()
+    _dev_tensor(points, torch.float32, "points")
+    off = np.ascontiguousarray(np.asarray(set_offsets, dtype=np.int64))
+    if off.ndim != 1 or off.shape[0] < 2 or points.numel() != 2 * int(off[-1]):
+        raise ValueError("points do not match set_offsets")
+    best = upper_hull_config()
+    ms = ctypes.c_float()
+    _check(load_library().upper_hull_autotune(_ptr(points), off.ctypes.data, off.shape[0] - 1,
+                                              flags, reps, ctypes.byref(best),
+                                              ctypes.byref(ms), _stream(stream)))
+    return {"strip": best.strip, "fan_in": best.fan_in, "flags": best.flags}, ms.value
 
 
 def upper_hull_bridge(P, Q, lanes=64, stream=None):

@@ -1321,6 +1321,59 @@ int upper_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_co
   return upper_hull_plan_run(p, points, out_idx, out_count, nullptr, stream);
 }
 
+int upper_hull_autotune(const float *points, const int64_t *set_offsets,
+                        int32_t num_sets, uint32_t flags, int32_t reps,
+                        upper_hull_config *best, float *best_ms,
+                        hipStream_t stream) {
+  if (!set_offsets || num_sets < 1 || !best || reps < 1 || reps > 1000) return UH_ERR_ARG;
+  const int64_t N = set_offsets[num_sets];
+  if (N > 0 && !points) return UH_ERR_ARG;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
+  if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
+  flags &= ~UH_FLAG_GRAPH;
+  int32_t *out_idx = nullptr, *out_counts = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = dalloc(&out_idx, (size_t)std::max<int64_t>(N, 1));
+  rc = rc ? rc : dalloc(&out_counts, (size_t)num_sets);
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = UH_ERR_HIP;
+  float best_t = -1.0f;
+  upper_hull_config chosen = {16, 256, flags};
+  static const int strips[] = {8, 16, 32}, fans[] = {16, 64, 256};
+  for (int si = 0; si < 3 && !rc; ++si) {
+    for (int fi = 0; fi < 3 && !rc; ++fi) {
+      const upper_hull_config cfg = {strips[si], fans[fi], flags};
+      upper_hull_plan *plan = nullptr;
+      rc = upper_hull_plan_create(set_offsets, num_sets, &cfg, &plan);
+      if (rc) break;
+      rc = upper_hull_plan_run(plan, points, out_idx, out_counts, nullptr, stream);  // untimed
+      if (!rc && hipEventRecord(e0, stream) != hipSuccess) rc = UH_ERR_HIP;
+      for (int r = 0; r < reps && !rc; ++r)
+        rc = upper_hull_plan_run(plan, points, out_idx, out_counts, nullptr, stream);
+      float ms = 0.0f;
+      if (!rc && (hipEventRecord(e1, stream) != hipSuccess ||
+                  hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = UH_ERR_HIP;
+      upper_hull_plan_destroy(plan);
+      ms /= (float)reps;
+      if (!rc && (best_t < 0.0f || ms < best_t)) {
+        best_t = ms;
+        chosen = cfg;
+      }
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipFree(out_idx);
+  hipFree(out_counts);
+  if (rc) return rc;
+  *best = chosen;
+  if (best_ms) *best_ms = best_t;
+  return UH_OK;
+}
+
 int upper_hull_bridge(const float *P, int32_t hp, const float *Q, int32_t hq,
                       int32_t lanes, int32_t *out_ab, hipStream_t stream) {
   if (!P || !Q || !out_ab || hp < 1 || hq < 1) return UH_ERR_ARG;

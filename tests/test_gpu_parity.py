@@ -5,6 +5,7 @@ bit-exact equality with the oracle (and, where noted, with brute force or
 the definitions in oracle.bridge).  All calls go through the C ABI via the
 thin Python binding.
 """
+import ctypes
 import itertools
 
 import numpy as np
@@ -271,6 +272,21 @@ def test_sets_whose_points_are_all_eliminated():
         assert np.array_equal(out[off[s]:off[s] + cnt[s]], ref)
     assert cnt[1] == uh.UH_ERR_RANGE and cnt[3] == uh.UH_ERR_RANGE
     assert cnt[4] == uh.UH_ERR_RANGE
+
+
+def test_autotune_picks_a_candidate_with_identical_results():
+    sets = [synth.uniform(150000, 20, seed=21), synth.arc(90001, 20, 4, seed=22),
+            synth.uniform(777, 20, seed=23)]
+    pts, off = synth.concat_sets(sets)
+    cfg, ms = uh.upper_hull_autotune(_dev(pts), off, reps=2)
+    assert cfg["strip"] in (8, 16, 32) and cfg["fan_in"] in (16, 64, 256)
+    assert cfg["flags"] == 0 and ms > 0
+    out, cnt = gpu_batched(pts, off, strip=cfg["strip"], fan_in=cfg["fan_in"])
+    assert_batched_equal(pts, off, out, cnt)
+    best = uh.upper_hull_config()
+    assert uh.load_library().upper_hull_autotune(
+        None, off.ctypes.data, len(off) - 1, 0, 0, ctypes.byref(best), None,
+        None) == uh.UH_ERR_ARG  # reps < 1
 
 
 def test_argument_errors():
