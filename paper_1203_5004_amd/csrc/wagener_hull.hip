@@ -6,7 +6,8 @@
 // back after every stage.  Here the same rounds of pairwise hood merges run
 // device-resident, in three kinds of launch enqueued back to back:
 //
-//   init_kernel   clears per-set status and counters.
+//   init_kernel   clears the stats counters and writes the counts of empty
+//                 sets (launched only when a run needs either).
 //   tile_kernel   one wave per tile of T = 64 * K points of one set:
 //                 coalesced load with the contract checks, strips of K
 //                 consecutive points per lane, an exact elimination of
@@ -53,6 +54,9 @@ constexpr int VMAX_WIDE = 12000; // ... and the wide one (one per CU)
 // sorted point list, not yet a hood); the merge kernel makes it a hood.
 constexpr uint32_t POINTS_FLAG = 0x80000000u;
 constexpr int TILE_LIST_MAX = 64;  // most survivors a tile hands on as a list
+// A group's maximum owns a 256-byte line of its own, so the atomics of the
+// tiles of different groups never queue behind one another.
+constexpr int GROUP_STRIDE = 64;
 
 struct TileItem {    // one tile of the tile pass (everything a tile needs: 32 bytes)
   int64_t start;     // first point (absolute)
@@ -62,16 +66,19 @@ struct TileItem {    // one tile of the tile pass (everything a tile needs: 32 b
   int16_t nb_lo;     // points of the set just before the tile used as witnesses, 0 .. 16
   int16_t nb_hi;     // points of the set just after it used as witnesses, 0 .. 16
   int32_t final_;    // 1 if this tile is its set's only tile
-  int32_t pad;
+  int32_t group;     // the first-level merge item that takes this tile (-1: none)
 };
 
 struct MergeItem {   // one workgroup of a merge pass
   int64_t off;       // slot start = first child's slot start (absolute)
   int64_t stride;    // child k's slot starts at off + k * stride
   int32_t child0;    // first child in the previous level's arrays
-  int32_t nch;       // children, 2 .. F
+  int32_t nch;       // children, 1 .. F
   int32_t set;
   int32_t final_;    // 1 if this is its set's last merge
+  int32_t g0, ng;    // the set's first-level merge items ("groups"): first, count
+  int32_t lvl0;      // 1 for a first-level item (its children are tiles)
+  int32_t pad;
 };
 
 struct RunArgs {
@@ -88,6 +95,9 @@ struct RunArgs {
   int64_t n_total;           // points over all sets (workspace length)
   int32_t tile_len;          // T
   int32_t one_set;           // 1: a single set, whose tiles follow from the tile index
+  int32_t group_fan;         //    ... and tile t belongs to group t / group_fan
+  uint32_t *tile_max;        // [tiles] each tile's highest y (order-preserving code)
+  uint32_t *group_max;       // [groups * GROUP_STRIDE] the highest y over each group's tiles (0: none)
   uint32_t flags;
 };
 
@@ -249,6 +259,17 @@ __device__ __forceinline__ void flush_wave_stats(const RunArgs &A, int set, Orie
   oc.evals = oc.fallbacks = 0;
 }
 
+// Order-preserving unsigned code of a float (larger float, larger code;
+// every code is positive, so 0 means "no value").
+__device__ __forceinline__ uint32_t y_code(float y) {
+  const uint32_t b = __float_as_uint(y);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float y_decode(uint32_t c) {
+  if (c == 0u) return -2.0f;  // below every valid y
+  return __uint_as_float((c & 0x80000000u) ? (c & 0x7fffffffu) : ~c);
+}
+
 __device__ __forceinline__ int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
   return v;
@@ -307,6 +328,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     it.nb_lo = (int16_t)min(16, it.rel0);
     it.nb_hi = (int16_t)min((int64_t)16, A.n_total - it.start - it.len);
     it.final_ = gridDim.x == 1;
+    it.group = it.final_ ? -1 : tile / A.group_fan;
   } else {
     it = items[tile];
   }
@@ -459,6 +481,14 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     }
   }
   const float incp = wave_prefix_max(ymax), incs = wave_suffix_max(ymax);
+  {
+    // the tile's highest point: a witness for the first merge level
+    const uint32_t code = y_code(readlane(incp, 63));
+    if (it.group >= 0 && lane == 0) {
+      A.tile_max[tile] = code;
+      atomicMax(&A.group_max[it.group * GROUP_STRIDE], code);
+    }
+  }
   const float exp_pre = fmaxf(dpp<DPP_WAVE_SHR1>(-2.0f, incp), nb_before);  // earlier strips
   const float exp_suf = fmaxf(dpp<DPP_WAVE_SHL1>(-2.0f, incs), nb_after);   // later strips
   const int rel0 = it.rel0;
@@ -637,6 +667,30 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &tota
   return before + x - v;
 }
 
+// Workgroup-wide exclusive maxima of v: over the threads below (pre) and
+// above (post) this one, each also at least the maximum of `all_pre` /
+// `all_post` over every thread of the workgroup.
+template <int BLK>
+__device__ __forceinline__ void block_excl_max(float v, float all_pre, float all_post,
+                                               float &pre, float &post, float4 *sw) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const float incp = wave_prefix_max(v), incs = wave_suffix_max(v);
+  const float ap = readlane(wave_prefix_max(all_pre), 63);
+  const float aq = readlane(wave_prefix_max(all_post), 63);
+  if (lane == 0) sw[w] = make_float4(readlane(incp, 63), readlane(incs, 0), ap, aq);
+  pre = dpp<DPP_WAVE_SHR1>(-2.0f, incp);
+  post = dpp<DPP_WAVE_SHL1>(-2.0f, incs);
+  __syncthreads();
+  for (int k = 0; k < BLK / 64; ++k) {
+    const float4 q = sw[k];
+    if (k < w) pre = fmaxf(pre, q.x);
+    if (k > w) post = fmaxf(post, q.y);
+    pre = fmaxf(pre, q.z);
+    post = fmaxf(post, q.w);
+  }
+  __syncthreads();  // sw may be reused
+}
+
 // One workgroup of BLK threads merges the hoods of up to BLK consecutive
 // blocks of the previous level of one set (log2 BLK more rounds).  When their corners fit
 // in LDS: gather them back to back, six rounds inside each wave (64
@@ -654,6 +708,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   __shared__ int2 sblk[BLK];  // LDS path: (base, count) per child block
   __shared__ int2 sres[BLK / 2];
   __shared__ int swave[BLK / 64 + 1];
+  __shared__ float4 sw4[BLK / 64];
 
   const MergeItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
@@ -669,9 +724,29 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   constexpr int PRE = 16;
   const int64_t g = it.off + (int64_t)tid * it.stride;
   const uint32_t craw = tid < nch ? (uint32_t)child_cnt[it.child0 + tid] : 0u;
+  const bool lvl0 = it.lvl0 != 0;
   float2 vx[16];
   int32_t vi[16];
-  {
+  // First level: every tile's highest y and every other group's are
+  // witnesses (actual points of the set, earlier or later than this
+  // workgroup's children).  A child tile whose highest point beats neither
+  // the earlier nor the later witnesses holds no corner and is not read.
+  float wpre = -2.0f, wsuf = -2.0f;  // witnesses for this thread's child
+  bool cand = true;
+  if (lvl0) {
+    const float tm = tid < nch ? y_decode(A.tile_max[it.child0 + tid]) : -2.0f;
+    float gp = -2.0f, gs = -2.0f;
+    for (int k = tid; k < it.ng; k += BLK) {
+      const int gi = it.g0 + k;
+      if (gi != (int)blockIdx.x) {
+        const float v = y_decode(A.group_max[gi * GROUP_STRIDE]);
+        if (gi < (int)blockIdx.x) gp = fmaxf(gp, v);
+        else gs = fmaxf(gs, v);
+      }
+    }
+    block_excl_max<BLK>(tm, gp, gs, wpre, wsuf, sw4);
+    cand = tm > wpre || tm >= wsuf;
+  } else {
     const int64_t last = A.n_total - 1;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -685,7 +760,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     }
   }
   const bool pts = (craw & POINTS_FLAG) != 0;
-  const int c = (int)(craw & ~POINTS_FLAG);
+  const int c = cand ? (int)(craw & ~POINTS_FLAG) : 0;
   int V;
   const int o = block_exclusive_scan<BLK>(c, swave, V);
   bcnt[tid] = c;
@@ -698,16 +773,18 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   if (V <= VMX) {
     // ---- gather: the prefetched entries to their places, then thread k
     // copies whatever child k has beyond them, eight loads in flight
+    if (!lvl0) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int ck = (w << 6) + 4 * u + (lane >> 4), e = lane & 15;
-      if (ck < nch && e < bcnt[ck]) {
-        bxy[soff[ck] + e] = vx[u];
-        bid[soff[ck] + e] = vi[u];
+      for (int u = 0; u < 16; ++u) {
+        const int ck = (w << 6) + 4 * u + (lane >> 4), e = lane & 15;
+        if (ck < nch && e < bcnt[ck]) {
+          bxy[soff[ck] + e] = vx[u];
+          bid[soff[ck] + e] = vi[u];
+        }
       }
     }
     if (tid < nch) {
-      for (int e0 = PRE; e0 < c; e0 += 8) {
+      for (int e0 = lvl0 ? 0 : PRE; e0 < c; e0 += 8) {
         float2 vx[8];
         int32_t vi[8];
 #pragma unroll
@@ -734,25 +811,17 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     // in place; what is left of a strictly concave chain is still one, so
     // every child stays a hood.
     {
-      float cmax = -2.0f;
-      for (int e0 = 0; e0 < c; e0 += 8) {  // eight LDS reads in flight
-        float yv[8];
+      float pre = wpre, suf = wsuf;
+      if (!lvl0) {  // witnesses: the children's highest corners
+        float cmax = -2.0f;
+        for (int e0 = 0; e0 < c; e0 += 8) {  // eight LDS reads in flight
+          float yv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) yv[u] = e0 + u < c ? bxy[o + e0 + u].y : -2.0f;
+          for (int u = 0; u < 8; ++u) yv[u] = e0 + u < c ? bxy[o + e0 + u].y : -2.0f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) cmax = fmaxf(cmax, yv[u]);
-      }
-      const float incp = wave_prefix_max(cmax), incs = wave_suffix_max(cmax);
-      __shared__ float swp[BLK / 64], sws[BLK / 64];
-      if (lane == 63) swp[w] = incp;
-      if (lane == 0) sws[w] = incs;
-      float pre = __shfl_up(incp, 1, 64), suf = __shfl_down(incs, 1, 64);
-      if (lane == 0) pre = -2.0f;
-      if (lane == 63) suf = -2.0f;
-      __syncthreads();
-      for (int k = 0; k < BLK / 64; ++k) {
-        if (k < w) pre = fmaxf(pre, swp[k]);
-        if (k > w) suf = fmaxf(suf, sws[k]);
+          for (int u = 0; u < 8; ++u) cmax = fmaxf(cmax, yv[u]);
+        }
+        block_excl_max<BLK>(cmax, -2.0f, -2.0f, pre, suf, sw4);
       }
       int kept = 0;
       for (int e0 = 0; e0 < c; e0 += 8) {  // a batch is read before it is rewritten
@@ -838,6 +907,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         if (lane == 0) {
           const int st = A.set_status[it.set];
           A.out_counts[it.set] = st ? st : hc;
+          if (st) A.set_status[it.set] = 0;  // zero again for the next run
         }
       } else {
         for (int k = lane; k < hc; k += 64) {
@@ -847,6 +917,8 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         if (lane == 0) cnt_out[blockIdx.x] = hc;
       }
     }
+    if (it.final_)  // the set's group maxima, zero again for the next run
+      for (int k = tid; k < it.ng; k += BLK) A.group_max[(it.g0 + k) * GROUP_STRIDE] = 0u;
     flush_wave_stats(A, it.set, oc);
     return;
   }
@@ -952,10 +1024,13 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     if (tid == 0) {
       const int st = A.set_status[it.set];
       A.out_counts[it.set] = st ? st : hc;
+      if (st) A.set_status[it.set] = 0;  // zero again for the next run
     }
   } else {
     if (tid == 0) cnt_out[blockIdx.x] = hc;
   }
+  if (it.final_)  // the set's group maxima, zero again for the next run
+    for (int k = tid; k < it.ng; k += BLK) A.group_max[(it.g0 + k) * GROUP_STRIDE] = 0u;
   flush_wave_stats(A, it.set, oc);
 }
 
@@ -993,6 +1068,10 @@ struct upper_hull_plan {
   int K = 16, T = 4096, F = 256;
   uint32_t flags = 0;
   int32_t ntiles = 0;
+  bool has_empty = false;  // some set has no points
+  int32_t ngroups = 0;     // first-level merge items
+  int32_t group_fan = 1;   // single set: tiles per group
+  uint32_t *tile_max = nullptr, *group_max = nullptr;
   std::vector<int32_t> pass_items;  // merge items per pass
   std::vector<char> pass_wide;      // per pass: some item has more than BLOCK children
   // device memory
@@ -1040,12 +1119,17 @@ void free_plan_memory(upper_hull_plan *p) {
   hipFree(p->ws2_xy);
   hipFree(p->ws2_idx);
   hipFree(p->set_status);
+  hipFree(p->tile_max);
+  hipFree(p->group_max);
   for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
 }
 
 int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
-  {
+  // Per-set status starts at zero (plan creation) and the final merge of a
+  // set that saw an error zeroes it again, so the clearing pass is needed
+  // only for stats counters and for empty sets' counts.
+  if (A.stats || p->has_empty) {
     const int nb = (p->S + 255) / 256;
     hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, stream, p->S, A);
   }
@@ -1142,14 +1226,16 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       it.nb_lo = (int16_t)std::min<int64_t>(16, t * p->T);
       it.nb_hi = (int16_t)std::min<int64_t>(16, n - t * p->T - it.len);
       it.final_ = nt == 1;
-      it.pad = 0;
+      it.group = -1;  // set below, once the first merge level is known
       tiles.push_back(it);
     }
   }
   p->ntiles = (int32_t)tiles.size();
+  for (int32_t s = 0; s < num_sets; ++s) p->has_empty = p->has_empty || set_offsets[s + 1] == set_offsets[s];
   // Within a set the blocks of a level are consecutive and equally long
   // (except the last), so child k of an item starts at off + k * stride.
   std::vector<std::vector<MergeItem>> passes;
+  std::vector<int32_t> g0(num_sets, 0), ng(num_sets, 0), fs0(num_sets, F);  // first level per set
   int64_t stride = p->T;
   for (;;) {
     std::vector<MergeItem> items;
@@ -1173,9 +1259,16 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
         m.stride = stride;
         m.set = s;
         m.final_ = nitems == 1;
+        m.lvl0 = passes.empty();
+        m.g0 = m.ng = m.pad = 0;
         items.push_back(m);
       }
       ncount[s] = nitems;
+      if (passes.empty()) {
+        g0[s] = nfirst[s];
+        ng[s] = nitems;
+        fs0[s] = FS;
+      }
     }
     if (items.empty()) break;
     passes.push_back(items);
@@ -1185,6 +1278,22 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     for (int32_t s = 0; s < num_sets; ++s) count[s] = ncount[s];
   }
 
+  // groups: the first-level items; every item knows its set's groups, and
+  // every tile of a set with more than one tile knows its group
+  for (auto &items : passes)
+    for (MergeItem &m : items) {
+      m.g0 = g0[m.set];
+      m.ng = ng[m.set];
+    }
+  for (int32_t s = 0, t0 = 0; s < num_sets; ++s) {
+    const int64_t n = set_offsets[s + 1] - set_offsets[s];
+    const int32_t nt = (int32_t)((n + p->T - 1) / p->T);
+    if (nt > 1)
+      for (int32_t t = 0; t < nt; ++t) tiles[t0 + t].group = g0[s] + t / fs0[s];
+    t0 += nt;
+  }
+  p->group_fan = fs0[0];
+  p->ngroups = passes.empty() ? 0 : (int32_t)passes[0].size();
   int rc = UH_OK;
   std::vector<int64_t> so(set_offsets, set_offsets + num_sets + 1);
   rc = rc ? rc : dalloc(&p->d_set_start, so.size());
@@ -1211,6 +1320,14 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   rc = rc ? rc : dalloc(&p->ws2_xy, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws2_idx, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->set_status, (size_t)num_sets);
+  rc = rc ? rc : dalloc(&p->tile_max, (size_t)p->ntiles);
+  rc = rc ? rc : dalloc(&p->group_max, (size_t)p->ngroups * GROUP_STRIDE);
+  if (!rc && p->ngroups > 0 &&
+      hipMemset(p->group_max, 0, (size_t)p->ngroups * GROUP_STRIDE * sizeof(uint32_t)) !=
+          hipSuccess)
+    rc = UH_ERR_HIP;
+  if (!rc && hipMemset(p->set_status, 0, (size_t)num_sets * sizeof(int32_t)) != hipSuccess)
+    rc = UH_ERR_HIP;
   if (rc) {
     free_plan_memory(p);
     delete p;
@@ -1222,7 +1339,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
 
 int upper_hull_plan_launches(const upper_hull_plan *plan) {
   if (!plan) return UH_ERR_ARG;
-  return 1 + (plan->ntiles > 0) + (int)plan->pass_items.size();
+  return (int)plan->has_empty + (plan->ntiles > 0) + (int)plan->pass_items.size();
 }
 
 int upper_hull_plan_set_probe(upper_hull_plan *plan, hipEvent_t before,
@@ -1251,6 +1368,9 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   A.stats = stats;
   A.n_total = p->N;
   A.tile_len = p->T;
+  A.group_fan = p->group_fan;
+  A.tile_max = p->tile_max;
+  A.group_max = p->group_max;
   A.one_set = p->S == 1;
   A.flags = p->flags;
   if (!(p->flags & UH_FLAG_GRAPH)) return enqueue_run(p, A, stream);
