@@ -77,7 +77,7 @@ struct MergeItem {   // one workgroup of a merge pass
   int32_t set;
   int32_t final_;    // 1 if this is its set's last merge
   int32_t g0, ng;    // the set's first-level merge items ("groups"): first, count
-  int32_t lvl0;      // 1 for a first-level item (its children are tiles)
+  int32_t level;     // 0: the children are tiles, 1: groups, 2: deeper
   int32_t pad;
 };
 
@@ -724,28 +724,34 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   constexpr int PRE = 16;
   const int64_t g = it.off + (int64_t)tid * it.stride;
   const uint32_t craw = tid < nch ? (uint32_t)child_cnt[it.child0 + tid] : 0u;
-  const bool lvl0 = it.lvl0 != 0;
+  // First two levels: the highest y of every child (a tile, or a group of
+  // tiles) and of every group of the set outside this item are witnesses
+  // (actual points of the set, earlier or later than the child).  A child
+  // whose highest point beats neither the earlier nor the later witnesses
+  // holds no corner and is not read.
+  const bool known_max = it.level <= 1;
   float2 vx[16];
   int32_t vi[16];
-  // First level: every tile's highest y and every other group's are
-  // witnesses (actual points of the set, earlier or later than this
-  // workgroup's children).  A child tile whose highest point beats neither
-  // the earlier nor the later witnesses holds no corner and is not read.
   float wpre = -2.0f, wsuf = -2.0f;  // witnesses for this thread's child
   bool cand = true;
-  if (lvl0) {
-    const float tm = tid < nch ? y_decode(A.tile_max[it.child0 + tid]) : -2.0f;
+  if (known_max) {
+    const float cm = tid >= nch ? -2.0f
+                     : it.level == 0 ? y_decode(A.tile_max[it.child0 + tid])
+                                     : y_decode(A.group_max[(it.child0 + tid) * GROUP_STRIDE]);
+    // the groups this item covers: its own (level 0) or its children (level 1)
+    const int glo = it.level == 0 ? (int)blockIdx.x : it.child0;
+    const int ghi = it.level == 0 ? (int)blockIdx.x : it.child0 + nch - 1;
     float gp = -2.0f, gs = -2.0f;
     for (int k = tid; k < it.ng; k += BLK) {
       const int gi = it.g0 + k;
-      if (gi != (int)blockIdx.x) {
+      if (gi < glo || gi > ghi) {
         const float v = y_decode(A.group_max[gi * GROUP_STRIDE]);
-        if (gi < (int)blockIdx.x) gp = fmaxf(gp, v);
+        if (gi < glo) gp = fmaxf(gp, v);
         else gs = fmaxf(gs, v);
       }
     }
-    block_excl_max<BLK>(tm, gp, gs, wpre, wsuf, sw4);
-    cand = tm > wpre || tm >= wsuf;
+    block_excl_max<BLK>(cm, gp, gs, wpre, wsuf, sw4);
+    cand = cm > wpre || cm >= wsuf;
   } else {
     const int64_t last = A.n_total - 1;
 #pragma unroll
@@ -773,7 +779,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   if (V <= VMX) {
     // ---- gather: the prefetched entries to their places, then thread k
     // copies whatever child k has beyond them, eight loads in flight
-    if (!lvl0) {
+    if (!known_max) {
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int ck = (w << 6) + 4 * u + (lane >> 4), e = lane & 15;
@@ -784,7 +790,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       }
     }
     if (tid < nch) {
-      for (int e0 = lvl0 ? 0 : PRE; e0 < c; e0 += 8) {
+      for (int e0 = known_max ? 0 : PRE; e0 < c; e0 += 8) {
         float2 vx[8];
         int32_t vi[8];
 #pragma unroll
@@ -812,7 +818,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     // every child stays a hood.
     {
       float pre = wpre, suf = wsuf;
-      if (!lvl0) {  // witnesses: the children's highest corners
+      if (!known_max) {  // witnesses: the children's highest corners
         float cmax = -2.0f;
         for (int e0 = 0; e0 < c; e0 += 8) {  // eight LDS reads in flight
           float yv[8];
@@ -1259,7 +1265,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
         m.stride = stride;
         m.set = s;
         m.final_ = nitems == 1;
-        m.lvl0 = passes.empty();
+        m.level = std::min<int32_t>((int32_t)passes.size(), 2);
         m.g0 = m.ng = m.pad = 0;
         items.push_back(m);
       }
