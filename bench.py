@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the plain per-set method (one plan per set, launched "
                          "set by set from the host) against the batched plan")
+    ap.add_argument("--read-reference", action="store_true",
+                    help="also time the library's plain streaming read of the same input: the "
+                         "bandwidth a simple read reaches on this GPU")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (scale reference for "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -234,6 +237,13 @@ def main():
                  "batched_speedup": round(gpu_ms / ms_step, 2), "same_counts": plain_ok}
         log(f"[bench] plain: {gpu_ms:.3f} ms/step -> batched is {gpu_ms / ms_step:.2f}x faster")
 
+    read_ref = None
+    if args.read_reference:
+        rms = uh.upper_hull_read_reference(pts, reps=20)
+        read_ref = {"what": "plain coalesced read of the same points (upper_hull_read_reference)",
+                    "ms": round(rms, 4), "GB/s": round(8.0 * N / (rms * 1e-3) / 1e9, 1)}
+        log(f"[bench] plain read of the input: {rms:.4f} ms = {read_ref['GB/s']} GB/s")
+
     h_total = int(cnt_np.sum())
     alg_tile = 8.0 * N  # every point read once (float2)
     roofline = None
@@ -243,7 +253,8 @@ def main():
         roofline = {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "tile_kernel_ms": round(tile_ms, 4)}
+                    "traffic": traffic, "tile_kernel_ms": round(tile_ms, 4),
+                    "plain_read": read_ref}
     path_gbs = (8.0 * N + 4.0 * h_total) / (ms_step * 1e-3) / 1e9
 
     cpu = None

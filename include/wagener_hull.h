@@ -181,6 +181,17 @@ int upper_hull_autotune(const float *points, const int64_t *set_offsets,
                         upper_hull_config *best, float *best_ms,
                         hipStream_t stream);
 
+/*
+ * Measurement aid: the mean time (*ms) of a plain coalesced streaming read
+ * of points[0 .. n) (whole 16-byte pairs; device, 16-byte aligned, n >= 2),
+ * over `reps` launches (1 .. 1000) after one untimed launch on `stream`.
+ * The tile kernel reads the same bytes, so 8 n / ms is the bandwidth a
+ * simple read reaches on this device for this buffer.  Synchronous;
+ * allocates 4 bytes of scratch while it runs.
+ */
+int upper_hull_read_reference(const float *points, int64_t n, int32_t reps, float *ms,
+                              hipStream_t stream);
+
 /* ------------------------------------------------------- building blocks */
 /*
  * The bridge of two hoods (match-and-merge, steps mam1-mam5 of the paper,

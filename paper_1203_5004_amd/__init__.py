@@ -36,7 +36,7 @@ UH_FLAG_GRAPH = 4
 EXPORTS = (
     "upper_hull_status_string", "upper_hull", "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
-    "upper_hull_plan_set_probe", "upper_hull_autotune",
+    "upper_hull_plan_set_probe", "upper_hull_autotune", "upper_hull_read_reference",
     "upper_hull_bridge", "upper_hull_orient",
 )
 
@@ -80,6 +80,8 @@ def load_library():
     lib.upper_hull_plan_set_probe.restype = ctypes.c_int
     lib.upper_hull_autotune.argtypes = [p, p, i32, ctypes.c_uint32, i32, p, p, p]
     lib.upper_hull_autotune.restype = ctypes.c_int
+    lib.upper_hull_read_reference.argtypes = [p, i64, i32, p, p]
+    lib.upper_hull_read_reference.restype = ctypes.c_int
     lib.upper_hull_bridge.argtypes = [p, i32, p, i32, i32, p, p]
     lib.upper_hull_bridge.restype = ctypes.c_int
     lib.upper_hull_orient.argtypes = [p, p, p, i64, p, p, i32, p]
@@ -215,6 +217,16 @@ def upper_hull_autotune(points, set_offsets, flags=0, reps=3, stream=None):
                                               flags, reps, ctypes.byref(best),
                                               ctypes.byref(ms), _stream(stream)))
     return {"strip": best.strip, "fan_in": best.fan_in, "flags": best.flags}, ms.value
+
+
+def upper_hull_read_reference(points, reps=20, stream=None):
+    """Mean ms of a plain streaming read of `points` (cuda float32 [N, 2])."""
+    torch = _torch()
+    _dev_tensor(points, torch.float32, "points")
+    ms = ctypes.c_float()
+    _check(load_library().upper_hull_read_reference(_ptr(points), points.numel() // 2, reps,
+                                                    ctypes.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def upper_hull_bridge(P, Q, lanes=64, stream=None):

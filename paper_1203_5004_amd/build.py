@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "wagener_hull.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "uh_device.hpp"),
+SOURCES = [SRC, os.path.join(HERE, "csrc", "read_reference.hip")]
+DEPS = [*SOURCES, os.path.join(HERE, "csrc", "uh_device.hpp"),
         os.path.join(ROOT, "include", "wagener_hull.h")]
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libwagener_hull.so")
@@ -38,7 +39,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(HERE, "csrc"), SRC, "-o", tmp]
+           "-I", os.path.join(HERE, "csrc"), *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

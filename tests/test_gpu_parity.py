@@ -289,6 +289,18 @@ def test_autotune_picks_a_candidate_with_identical_results():
         None) == uh.UH_ERR_ARG  # reps < 1
 
 
+def test_read_reference_times_a_read_and_checks_its_arguments():
+    pts = _dev(synth.uniform(1 << 20, 20, seed=31))
+    ms = uh.upper_hull_read_reference(pts, reps=3)
+    assert 0 < ms < 100
+    lib, out = uh.load_library(), ctypes.c_float(-1)
+    base = pts.data_ptr()
+    assert lib.upper_hull_read_reference(base + 8, 100, 1, ctypes.byref(out), None) \
+        == uh.UH_ERR_ARG  # not 16-byte aligned
+    assert lib.upper_hull_read_reference(base, 1, 1, ctypes.byref(out), None) == uh.UH_ERR_ARG
+    assert lib.upper_hull_read_reference(base, 100, 0, ctypes.byref(out), None) == uh.UH_ERR_ARG
+
+
 def test_argument_errors():
     with pytest.raises(RuntimeError):
         uh.upper_hull_plan_create([0, 5, 3])
