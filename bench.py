@@ -116,6 +116,10 @@ def main():
     ap.add_argument("--read-reference", action="store_true",
                     help="also time the library's plain streaming read of the same input: the "
                          "bandwidth a simple read reaches on this GPU")
+    ap.add_argument("--flush", action="store_true",
+                    help="cold caches: overwrite a 1 GiB buffer before every timed step (outside "
+                         "the step's own events), so the input is read from HBM, not the 256 MB "
+                         "last-level cache")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (scale reference for "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -188,15 +192,33 @@ def main():
 
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for k in range(args.steps):
-        if probes:
-            plan.set_probe(*probes[k])
-        plan.run(pts, out_idx, out_cnt)
-    end.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
+    if args.flush:
+        # every step bracketed by its own events; the cache-clearing write between steps
+        # is outside them
+        scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        for k in range(args.steps):
+            scratch.fill_(float(k))
+            if probes:
+                plan.set_probe(*probes[k])
+            marks[k][0].record()
+            plan.run(pts, out_idx, out_cnt)
+            marks[k][1].record()
+        torch.cuda.synchronize()
+        total_ms = sum(a.elapsed_time(b) for a, b in marks)
+        del scratch
+    else:
+        torch.cuda.synchronize()
+        start.record()
+        for k in range(args.steps):
+            if probes:
+                plan.set_probe(*probes[k])
+            plan.run(pts, out_idx, out_cnt)
+        end.record()
+        torch.cuda.synchronize()
+        total_ms = start.elapsed_time(end)
     ms_step = total_ms / args.steps
     value = N / (ms_step * 1e-3)
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} points/s")
@@ -280,6 +302,7 @@ def main():
                    "tile_points": 64 * args.strip, "launches_per_step": plan.launches,
                    "fan_in": fan_in or 256, "autotuned": tuned,
                    "graph": bool(args.graph), "force_fallback": bool(args.force_fallback),
+                   "cold_cache": bool(args.flush),
                    "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),
                    "fallback_rate": (fallbacks / evals) if evals else 0.0,

@@ -1,4 +1,5 @@
-"""CPU oracle for the upper hood -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for the upper and lower hoods and the convex hull -- TEST
+INFRASTRUCTURE ONLY.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
 leg may import this package.  The GPU library never loads it and shares no
@@ -7,7 +8,8 @@ code with it; the two meet only through the seeded generators in ``synth``.
 Contents:
   * ``hull_oracle.c`` (built into ``_build/liboracle_hull.so``): the exact
     integer Andrew monotone chain (upper half) -- the plain definition of the
-    upper hood the method computes;
+    upper hood the method computes -- the lower hood as its mirror image, and
+    the convex hull assembled from both (counter-clockwise);
   * ``brute``      -- O(n^3) evaluation of the hood's definition (tiny n);
   * ``invariants`` -- exact checks that characterise the strict upper hood;
   * ``bridge``     -- the per-merge quantities of the paper's match-and-merge
@@ -60,6 +62,11 @@ def _load():
         lib.oracle_upper_hull.restype = ctypes.c_int
         lib.oracle_upper_hull_batched.argtypes = [p, p, i64, p, p]
         lib.oracle_upper_hull_batched.restype = ctypes.c_int
+        for name in ("oracle_lower_hull", "oracle_convex_hull"):
+            getattr(lib, name).argtypes = [p, i64, p, p]
+            getattr(lib, name).restype = ctypes.c_int
+        lib.oracle_lower_hull_batched.argtypes = [p, p, i64, p, p]
+        lib.oracle_lower_hull_batched.restype = ctypes.c_int
         lib.oracle_orient_signs.argtypes = [p, p, p, i64, p]
         lib.oracle_orient_signs.restype = ctypes.c_int
         _lib = lib
@@ -71,15 +78,29 @@ def _pts(xy) -> np.ndarray:
     return a
 
 
-def upper_hull_status(xy):
-    """(status, indices).  status 0 on success, else a negative error code."""
+def _single(name, xy):
     a = _pts(xy)
     n = a.shape[0]
     out = np.empty(max(n, 1), dtype=np.int32)
     cnt = ctypes.c_int64(0)
-    rc = _load().oracle_upper_hull(a.ctypes.data, n, out.ctypes.data,
-                                   ctypes.addressof(cnt))
+    rc = getattr(_load(), name)(a.ctypes.data, n, out.ctypes.data, ctypes.addressof(cnt))
     return rc, out[: cnt.value].copy()
+
+
+def upper_hull_status(xy):
+    """(status, indices).  status 0 on success, else a negative error code."""
+    return _single("oracle_upper_hull", xy)
+
+
+def lower_hull_status(xy):
+    """(status, indices) of the lower hood (corners left to right)."""
+    return _single("oracle_lower_hull", xy)
+
+
+def convex_hull_status(xy):
+    """(status, indices) of the convex hull, counter-clockwise from the lowest
+    point of least x."""
+    return _single("oracle_convex_hull", xy)
 
 
 def upper_hull(xy) -> np.ndarray:
@@ -90,19 +111,44 @@ def upper_hull(xy) -> np.ndarray:
     return idx
 
 
-def upper_hull_batched(xy, offsets):
-    """Per-set hulls.  Returns (out_idx, counts): set s's corner indices,
-    relative to offsets[s], are out_idx[offsets[s] : offsets[s] + counts[s]]."""
+def lower_hull(xy) -> np.ndarray:
+    """Indices of the strict lower-hood corners, left to right (int32)."""
+    rc, idx = lower_hull_status(xy)
+    if rc != OK:
+        raise ValueError(f"oracle: invalid input (status {rc})")
+    return idx
+
+
+def convex_hull(xy) -> np.ndarray:
+    """Indices of the convex hull's corners, counter-clockwise (int32)."""
+    rc, idx = convex_hull_status(xy)
+    if rc != OK:
+        raise ValueError(f"oracle: invalid input (status {rc})")
+    return idx
+
+
+def _batched(name, xy, offsets):
     a = _pts(xy)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     S = off.shape[0] - 1
     out = np.zeros(max(a.shape[0], 1), dtype=np.int32)
     counts = np.zeros(max(S, 1), dtype=np.int64)
-    rc = _load().oracle_upper_hull_batched(a.ctypes.data, off.ctypes.data, S,
-                                           out.ctypes.data, counts.ctypes.data)
+    rc = getattr(_load(), name)(a.ctypes.data, off.ctypes.data, S,
+                                out.ctypes.data, counts.ctypes.data)
     if rc != OK:
         raise ValueError(f"oracle: invalid input (status {rc})")
     return out, counts[:S]
+
+
+def upper_hull_batched(xy, offsets):
+    """Per-set hulls.  Returns (out_idx, counts): set s's corner indices,
+    relative to offsets[s], are out_idx[offsets[s] : offsets[s] + counts[s]]."""
+    return _batched("oracle_upper_hull_batched", xy, offsets)
+
+
+def lower_hull_batched(xy, offsets):
+    """Per-set lower hoods, laid out as in ``upper_hull_batched``."""
+    return _batched("oracle_lower_hull_batched", xy, offsets)
 
 
 def orient_signs(a, b, c) -> np.ndarray:

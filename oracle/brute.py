@@ -1,4 +1,5 @@
-"""O(n^3) evaluation of the upper hood's definition -- TEST INFRASTRUCTURE.
+"""Brute-force evaluation of the hoods' and the hull's definitions -- TEST
+INFRASTRUCTURE.
 
 For tiny inputs only.  Follows the paper's problem statement (the upper hood
 of points in left-to-right order) and its orientation convention (r is left
@@ -17,6 +18,8 @@ Corners are returned in index order (which is left-to-right order).
 Coordinates are converted to exact Python integers on the 2^-30 grid.
 """
 from __future__ import annotations
+
+import itertools
 
 import numpy as np
 
@@ -58,5 +61,59 @@ def upper_hull_brute(xy) -> list:
             if covered:
                 break
         if not covered:
+            out.append(i)
+    return out
+
+
+def lower_hull_brute(xy) -> list:
+    """The lower hood's definition, evaluated directly: point i is a corner
+    iff it is the lowest point at its x (identical points: lowest index) and
+    no pair a, b with X_a < X_i < X_b has i on or above segment ab."""
+    X, Y = exact_ints(xy)
+    n = len(X)
+    out = []
+    for i in range(n):
+        if any(j != i and X[j] == X[i] and (Y[j] < Y[i] or (Y[j] == Y[i] and j < i))
+               for j in range(n)):
+            continue
+        left = [a for a in range(n) if X[a] < X[i]]
+        right = [b for b in range(n) if X[b] > X[i]]
+        if not any(det(X, Y, a, b, i) >= 0 for a in left for b in right):
+            out.append(i)
+    return out
+
+
+def _on_segment(X, Y, a, b, i) -> bool:
+    return (det(X, Y, a, b, i) == 0 and min(X[a], X[b]) <= X[i] <= max(X[a], X[b])
+            and min(Y[a], Y[b]) <= Y[i] <= max(Y[a], Y[b]))
+
+
+def _in_triangle(X, Y, a, b, c, i) -> bool:
+    d = det(X, Y, a, b, c)
+    if d == 0:
+        return False  # degenerate: covered by the segment test
+    s = (det(X, Y, a, b, i), det(X, Y, b, c, i), det(X, Y, c, a, i))
+    return all(v >= 0 for v in s) if d > 0 else all(v <= 0 for v in s)
+
+
+def convex_hull_corners_brute(xy) -> list:
+    """The corner set of the convex hull, from its definition: point i is a
+    corner iff no identical point has a lower index and i does not lie in the
+    closed convex hull of the points at other positions -- in the plane, iff
+    it lies on no closed segment and in no closed triangle of such points
+    (Caratheodory).  Returned in index order (the order around the hull is
+    checked separately)."""
+    X, Y = exact_ints(xy)
+    n = len(X)
+    out = []
+    for i in range(n):
+        if any(X[j] == X[i] and Y[j] == Y[i] for j in range(i)):
+            continue
+        others = [j for j in range(n) if X[j] != X[i] or Y[j] != Y[i]]
+        inside = any(_on_segment(X, Y, a, b, i) for a, b in itertools.combinations(others, 2))
+        if not inside:
+            inside = any(_in_triangle(X, Y, a, b, c, i)
+                         for a, b, c in itertools.combinations(others, 3))
+        if not inside:
             out.append(i)
     return out

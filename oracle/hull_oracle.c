@@ -1,10 +1,11 @@
 /*
- * Upper-hood oracle -- TEST INFRASTRUCTURE ONLY.
+ * Hood and hull oracle -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow, obviously correct CPU computation of what the GPU path
  * computes: the upper hood (upper convex hull, closed by downward vertical
  * rays) of a set of points given in left-to-right order, returned as the
- * input indices of its corners, left to right.  Only the tests, the smoke
+ * input indices of its corners, left to right; the lower hood (its mirror
+ * image under y -> -y); and the whole convex hull assembled from the two.  Only the tests, the smoke
  * check and the benchmark's CPU baseline may load this library; the product
  * path never calls it.  It shares no code, header or constant generator with
  * the GPU library.
@@ -38,6 +39,16 @@
  *   2. keep one representative per run of equal x (max y, lowest index);
  *   3. scan representatives left to right, popping the stack top while the
  *      new point is on or above the line through the top two, then push.
+ *
+ * Lower hood and convex hull (the paper's title and abstract promise the 2-D
+ * convex hull; the method it details builds the upper hood only):
+ *   - the lower hood of a set is the reflection, under y -> -y, of the upper
+ *     hood of the reflected set, corner indices unchanged: at an x only the
+ *     lowest point can be a corner (ties to the lowest index), and a point on
+ *     or above the line through its neighbours is dropped;
+ *   - the convex hull, counter-clockwise from the lowest point of least x, is
+ *     the lower hood left to right followed by the upper hood right to left,
+ *     each hood's end corner omitted where the two hoods share it.
  *
  * The chain's correctness is not taken on trust: the tests pin it against an
  * O(n^3) brute-force evaluation of the hood's definition, against Qhull on
@@ -116,10 +127,10 @@ static int64_t chain(const int64_t *X, const int64_t *Y, int64_t n,
   return h;
 }
 
-/* Upper hood of xy[0..n) (x, y interleaved float32).  out_idx needs room for
- * n entries.  Returns 0 and sets *out_count, or a negative error code. */
-int oracle_upper_hull(const float *xy, int64_t n, int32_t *out_idx,
-                      int64_t *out_count) {
+/* The upper hood (lower = 0) or the lower hood (lower = 1) of xy[0..n):
+ * the lower hood is the upper hood of the points reflected in the x axis. */
+static int hood(const float *xy, int64_t n, int32_t *out_idx, int64_t *out_count,
+                int lower) {
   if (n < 0 || n > INT32_MAX || (n > 0 && (!xy || !out_idx)) || !out_count)
     return OR_ERR_ARG;
   *out_count = 0;
@@ -132,9 +143,51 @@ int oracle_upper_hull(const float *xy, int64_t n, int32_t *out_idx,
     return OR_ERR_ARG;
   }
   int rc = convert(xy, n, X, Y);
+  if (rc == OR_OK && lower)
+    for (int64_t i = 0; i < n; ++i) Y[i] = -Y[i];
   if (rc == OR_OK) *out_count = chain(X, Y, n, out_idx);
   free(X);
   free(Y);
+  return rc;
+}
+
+/* Upper hood of xy[0..n) (x, y interleaved float32).  out_idx needs room for
+ * n entries.  Returns 0 and sets *out_count, or a negative error code. */
+int oracle_upper_hull(const float *xy, int64_t n, int32_t *out_idx,
+                      int64_t *out_count) {
+  return hood(xy, n, out_idx, out_count, 0);
+}
+
+/* Lower hood of xy[0..n), corner indices left to right; as above. */
+int oracle_lower_hull(const float *xy, int64_t n, int32_t *out_idx,
+                      int64_t *out_count) {
+  return hood(xy, n, out_idx, out_count, 1);
+}
+
+/* Convex hull of xy[0..n): corner indices counter-clockwise, starting at the
+ * lowest point of least x (lowest index among identical points).  out_idx
+ * needs room for n entries (every index appears at most once). */
+int oracle_convex_hull(const float *xy, int64_t n, int32_t *out_idx,
+                       int64_t *out_count) {
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!xy || !out_idx)) || !out_count)
+    return OR_ERR_ARG;
+  *out_count = 0;
+  if (n == 0) return OR_OK;
+  int32_t *up = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  if (!up) return OR_ERR_ARG;
+  int64_t hl = 0, hu = 0;
+  int rc = hood(xy, n, out_idx, &hl, 1); /* lower hood, left to right */
+  if (rc == OR_OK) rc = hood(xy, n, up, &hu, 0);
+  if (rc == OR_OK) {
+    int64_t h = hl;
+    for (int64_t k = hu - 1; k >= 0; --k) { /* upper hood, right to left */
+      if (k == hu - 1 && up[k] == out_idx[hl - 1]) continue; /* shared right end */
+      if (k == 0 && up[k] == out_idx[0]) continue;           /* shared left end */
+      out_idx[h++] = up[k];
+    }
+    *out_count = h;
+  }
+  free(up);
   return rc;
 }
 
@@ -142,20 +195,31 @@ int oracle_upper_hull(const float *xy, int64_t n, int32_t *out_idx,
  * indices (relative to offsets[s]) are written at out_idx + offsets[s] and
  * its count to out_counts[s].  Returns 0 or the first error code; a set
  * that fails gets its error code as its count. */
-int oracle_upper_hull_batched(const float *xy, const int64_t *offsets,
-                              int64_t num_sets, int32_t *out_idx,
-                              int64_t *out_counts) {
+static int batched(const float *xy, const int64_t *offsets, int64_t num_sets,
+                   int32_t *out_idx, int64_t *out_counts, int lower) {
   if (num_sets < 0 || !offsets || (num_sets > 0 && !out_counts))
     return OR_ERR_ARG;
   int first_err = OR_OK;
   for (int64_t s = 0; s < num_sets; ++s) {
     int64_t lo = offsets[s], hi = offsets[s + 1];
     int64_t cnt = 0;
-    int rc = oracle_upper_hull(xy + 2 * lo, hi - lo, out_idx + lo, &cnt);
+    int rc = hood(xy + 2 * lo, hi - lo, out_idx + lo, &cnt, lower);
     out_counts[s] = rc ? rc : cnt;
     if (rc && !first_err) first_err = rc;
   }
   return first_err;
+}
+
+int oracle_upper_hull_batched(const float *xy, const int64_t *offsets,
+                              int64_t num_sets, int32_t *out_idx,
+                              int64_t *out_counts) {
+  return batched(xy, offsets, num_sets, out_idx, out_counts, 0);
+}
+
+int oracle_lower_hull_batched(const float *xy, const int64_t *offsets,
+                              int64_t num_sets, int32_t *out_idx,
+                              int64_t *out_counts) {
+  return batched(xy, offsets, num_sets, out_idx, out_counts, 1);
 }
 
 /* Exact sign of det(b - a, c - a) for m triples of float points (each array

@@ -2,9 +2,10 @@
 
 Each mutant is the oracle's C source with one plausible slip planted in it
 (a dropped term, a wrong sign or comparison, a transposed operand, a wrong
-tie rule, a missing check).  It is compiled with gcc into a temporary
+tie rule, a missing check, a slip in assembling the hull from its hoods).  It is compiled with gcc into a temporary
 library, and the pin suite below -- hand-derived fixtures, brute force on
-random lattices, closed forms and the contract's error codes -- must reject
+random lattices (upper and lower hood, hull corners and their order),
+closed forms and the contract's error codes -- must reject
 every one of them, while accepting the unmodified source.
 """
 import ctypes
@@ -15,7 +16,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import brute
+from oracle import brute, invariants
 from tests import golden_io
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
@@ -46,6 +47,14 @@ MUTANTS = {
         "if (i > 0 && X[i] < X[i - 1]) return OR_ERR_UNSORTED;", ""),
     "missing grid check": (
         "if (t != s) return OR_ERR_GRID;", ""),
+    "lower hood not mirrored": (
+        "if (rc == OR_OK && lower)", "if (rc == OR_OK && 0 && lower)"),
+    "hull keeps the shared right end twice": (
+        "if (k == hu - 1 && up[k] == out_idx[hl - 1]) continue;", ""),
+    "hull keeps the shared left end twice": (
+        "if (k == 0 && up[k] == out_idx[0]) continue;", ""),
+    "hull walks the upper hood left to right": (
+        "out_idx[h++] = up[k];", "out_idx[h++] = up[hu - 1 - k];"),
 }
 
 
@@ -56,19 +65,20 @@ def _compile(src_text, tmp_path, name):
     subprocess.check_call(["gcc", "-O1", "-std=c11", "-shared", "-fPIC", str(c),
                            "-o", str(so), "-lm"])
     lib = ctypes.CDLL(str(so))
-    lib.oracle_upper_hull.argtypes = [ctypes.c_void_p, ctypes.c_int64,
-                                      ctypes.c_void_p, ctypes.c_void_p]
-    lib.oracle_upper_hull.restype = ctypes.c_int
+    for name in ("oracle_upper_hull", "oracle_lower_hull", "oracle_convex_hull"):
+        getattr(lib, name).argtypes = [ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]
+        getattr(lib, name).restype = ctypes.c_int
     return lib
 
 
-def _run(lib, xy):
+def _run(lib, xy, name="oracle_upper_hull"):
     a = np.ascontiguousarray(np.asarray(xy, np.float32).reshape(-1, 2))
     out = np.zeros(max(a.shape[0], 1), np.int32)
     cnt = ctypes.c_int64(0)
-    rc = lib.oracle_upper_hull(a.ctypes.data, a.shape[0], out.ctypes.data,
-                               ctypes.addressof(cnt))
-    return rc, list(out[:cnt.value])
+    rc = getattr(lib, name)(a.ctypes.data, a.shape[0], out.ctypes.data,
+                            ctypes.addressof(cnt))
+    return rc, [int(i) for i in out[:cnt.value]]
 
 
 def _pins_pass(lib) -> bool:
@@ -80,6 +90,13 @@ def _pins_pass(lib) -> bool:
         xy = synth.lattice_points(1 + seed % 12, 8, seed=77 + seed)
         if _run(lib, xy) != (0, brute.upper_hull_brute(xy)):
             return False
+        if _run(lib, xy, "oracle_lower_hull") != (0, brute.lower_hull_brute(xy)):
+            return False
+        if seed % 3 == 0:  # the hull's brute force is O(n^4)
+            rc, got = _run(lib, xy, "oracle_convex_hull")
+            if rc != 0 or sorted(got) != brute.convex_hull_corners_brute(xy) or \
+                    invariants.check_convex_hull(xy, got):
+                return False
     if _run(lib, [[0.5, 0.0], [0.25, 0.0]])[0] != -10:
         return False
     if _run(lib, [[0.5, 2.0 ** -40]])[0] != -12:
