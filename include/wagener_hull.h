@@ -86,6 +86,9 @@ typedef struct {
                                   /* path (ablation / soundness tests)      */
 #define UH_FLAG_NO_VALIDATE 2u    /* skip the data-contract checks          */
 #define UH_FLAG_GRAPH 4u          /* replay the run as a captured hipGraph  */
+#define UH_FLAG_BOTH_HOODS 8u     /* also the lower hood of every set, from */
+                                  /* the same single read of the points     */
+                                  /* (output layout at upper_hull_plan_run) */
 
 /* ------------------------------------------------------------ single set */
 /*
@@ -97,14 +100,34 @@ typedef struct {
  *   out_count device int32[1]: the corner count, or a negative data-error
  *             status.
  *   stream    HIP stream the work is enqueued on.
- * The library keeps a plan (schedule + workspace of about 12 bytes per
+ * The library keeps a plan (schedule + workspace of about 24 bytes per
  * point) per distinct n, built on first use; building one is not allowed
  * while `stream` is capturing (UH_ERR_CAPTURE): call once before capture.
  * This is the paper's whole program (its stage loop and match_and_merge
- * launches) as one device-resident call.
+ * launches) as one device-resident call.  Calls for the same n share that
+ * plan's workspace, so calls on different streams must not overlap.
  */
 int upper_hull(const float *points, int64_t n, int32_t *out_idx,
                int32_t *out_count, hipStream_t stream);
+
+/*
+ * Convex hull of points[0..n), the 2-D hull the paper's title and abstract
+ * name: its corner indices counter-clockwise, starting at the lowest point of
+ * least x (identical points resolve to the lowest index).  The lower hood is
+ * the upper hood of the points mirrored in the x axis; both hoods come from
+ * one read of the points (UH_FLAG_BOTH_HOODS), then the lower hood left to
+ * right and the upper hood right to left, without the end corners the two
+ * share, are joined into out_idx.
+ *   points, n, stream   as for upper_hull.
+ *   out_idx    device int32[n]: every index appears at most once.
+ *   out_count  device int32[1]: the corner count, or a negative data-error
+ *              status (the same checks as upper_hull).
+ * Keeps its own cached plan per n (workspace about 48 bytes per point plus
+ * 8 bytes per point of hood buffers); the same rules as upper_hull apply
+ * (no plan building during capture, no overlapping calls for one n).
+ */
+int convex_hull(const float *points, int64_t n, int32_t *out_idx,
+                int32_t *out_count, hipStream_t stream);
 
 /* ------------------------------------------------------------ batched */
 typedef struct upper_hull_plan upper_hull_plan;
@@ -118,7 +141,8 @@ typedef struct upper_hull_plan upper_hull_plan;
  *   config       NULL for defaults.
  *   out_plan     receives the plan (owned by the caller; destroy it with
  *                upper_hull_plan_destroy).
- * Allocates the schedule tables and the workspace (about 12 bytes per point
+ * Allocates the schedule tables and the workspace (about 24 bytes per point,
+ * twice that with UH_FLAG_BOTH_HOODS,
  * plus a few bytes per tile) on the current device.
  */
 int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
@@ -136,6 +160,12 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
  *   stream      HIP stream.
  * With UH_FLAG_GRAPH the launch sequence is captured once per distinct
  * (points, out_idx, out_counts, stats) tuple and replayed as a hipGraph.
+ * With UH_FLAG_BOTH_HOODS every array holds two halves: out_idx has
+ * 2 * set_offsets[num_sets] entries, out_counts and stats 2 * num_sets; the
+ * upper hoods fill the first half as above, and the lower hood of set s
+ * (corners left to right, indices relative to set_offsets[s]) sits at
+ * out_idx + set_offsets[num_sets] + set_offsets[s], its count at
+ * out_counts[num_sets + s].  A data error is reported in both halves.
  */
 int upper_hull_plan_run(upper_hull_plan *plan, const float *points,
                         int32_t *out_idx, int32_t *out_counts,

@@ -1,4 +1,4 @@
-"""Python binding of the MI355X upper-hood library (libwagener_hull.so).
+"""Python binding of the MI355X upper-hood / convex-hull library (libwagener_hull.so).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels behind the C ABI declared in include/wagener_hull.h.  PyTorch
@@ -7,6 +7,7 @@ if the library has not been built, every call raises.
 
     import torch, paper_1203_5004_amd as uh
     idx, cnt = uh.upper_hull(points)          # points: cuda float32 [n, 2]
+    idx, cnt = uh.convex_hull(points)         # counter-clockwise hull corners
     plan = uh.upper_hull_plan_create(offsets) # host offsets, len S + 1
     plan.run(points, out_idx, out_counts, stats)
 """
@@ -32,9 +33,10 @@ UH_ERR_GRID = -12
 UH_FLAG_FORCE_FALLBACK = 1
 UH_FLAG_NO_VALIDATE = 2
 UH_FLAG_GRAPH = 4
+UH_FLAG_BOTH_HOODS = 8
 
 EXPORTS = (
-    "upper_hull_status_string", "upper_hull", "upper_hull_plan_create",
+    "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
     "upper_hull_plan_set_probe", "upper_hull_autotune", "upper_hull_read_reference",
     "upper_hull_bridge", "upper_hull_orient",
@@ -68,6 +70,8 @@ def load_library():
     lib.upper_hull_status_string.restype = ctypes.c_char_p
     lib.upper_hull.argtypes = [p, i64, p, p, p]
     lib.upper_hull.restype = ctypes.c_int
+    lib.convex_hull.argtypes = [p, i64, p, p, p]
+    lib.convex_hull.restype = ctypes.c_int
     lib.upper_hull_plan_create.argtypes = [p, i32, p, ctypes.POINTER(p)]
     lib.upper_hull_plan_create.restype = ctypes.c_int
     lib.upper_hull_plan_run.argtypes = [p, p, p, p, p, p]
@@ -129,6 +133,17 @@ def upper_hull(points, out_idx=None, out_count=None, stream=None):
     Returns (out_idx int32[n], out_count int32[1]) on the device; the first
     out_count[0] entries of out_idx are the corners, left to right (a
     negative count is a data-error status).  Asynchronous on `stream`."""
+    return _single("upper_hull", points, out_idx, out_count, stream)
+
+
+def convex_hull(points, out_idx=None, out_count=None, stream=None):
+    """Convex-hull corner indices of points (cuda float32 [n, 2], x-sorted),
+    counter-clockwise from the lowest point of least x; returned as for
+    ``upper_hull``."""
+    return _single("convex_hull", points, out_idx, out_count, stream)
+
+
+def _single(name, points, out_idx, out_count, stream):
     torch = _torch()
     _dev_tensor(points, torch.float32, "points")
     n = points.shape[0]
@@ -140,8 +155,10 @@ def upper_hull(points, out_idx=None, out_count=None, stream=None):
         out_count = torch.empty(1, dtype=torch.int32, device=points.device)
     _dev_tensor(out_idx, torch.int32, "out_idx")
     _dev_tensor(out_count, torch.int32, "out_count")
-    _check(load_library().upper_hull(_ptr(points), n, _ptr(out_idx), _ptr(out_count),
-                                     _stream(stream)))
+    if out_idx.numel() < n or out_count.numel() < 1:
+        raise ValueError("out_idx needs n entries and out_count one")
+    _check(getattr(load_library(), name)(_ptr(points), n, _ptr(out_idx), _ptr(out_count),
+                                         _stream(stream)))
     return out_idx, out_count
 
 
@@ -155,6 +172,8 @@ class Plan:
         self.set_offsets = off
         self.num_sets = off.shape[0] - 1
         self.total = int(off[-1])
+        # with both hoods every output array has two halves (upper, lower)
+        self.hoods = 2 if flags & UH_FLAG_BOTH_HOODS else 1
         cfg = upper_hull_config(strip, fan_in, flags)
         h = ctypes.c_void_p()
         _check(load_library().upper_hull_plan_create(
@@ -175,14 +194,14 @@ class Plan:
         _dev_tensor(points, torch.float32, "points")
         _dev_tensor(out_idx, torch.int32, "out_idx")
         _dev_tensor(out_counts, torch.int32, "out_counts")
-        if points.numel() != 2 * self.total or out_idx.numel() < self.total:
+        if points.numel() != 2 * self.total or out_idx.numel() < self.hoods * self.total:
             raise ValueError("buffer sizes do not match the plan")
-        if out_counts.numel() < self.num_sets:
+        if out_counts.numel() < self.hoods * self.num_sets:
             raise ValueError("out_counts too small")
         if stats is not None:
             _dev_tensor(stats, torch.int64, "stats")
-            if stats.numel() < 2 * self.num_sets:
-                raise ValueError("stats needs 2 int64 per set")
+            if stats.numel() < 2 * self.hoods * self.num_sets:
+                raise ValueError("stats needs 2 int64 per set and hood")
         _check(load_library().upper_hull_plan_run(
             self._h, _ptr(points), _ptr(out_idx), _ptr(out_counts), _ptr(stats),
             _stream(stream)))

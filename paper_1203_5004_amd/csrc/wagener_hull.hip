@@ -99,6 +99,12 @@ struct RunArgs {
   uint32_t *tile_max;        // [tiles] each tile's highest y (order-preserving code)
   uint32_t *group_max;       // [groups * GROUP_STRIDE] the highest y over each group's tiles (0: none)
   uint32_t flags;
+  int64_t n_points;          // input points (n_total, or half of it with both hoods)
+  // Both hoods: the lower hood of input set s is set s + lower_sets, its
+  // slots are the upper hood's plus lower_n, its tiles and groups are the
+  // upper ones' plus lower_tiles / lower_groups (all 0 otherwise).
+  int64_t lower_n;
+  int32_t lower_tiles, lower_groups, lower_sets;
 };
 
 // ------------------------------------------------------------ small helpers
@@ -279,11 +285,12 @@ __device__ __forceinline__ int wave_min(int v) {
 // T = 64 * K points of one set; no workgroup barrier anywhere.
 //  1. coalesced 16-byte loads (two points per lane per load) and the data
 //     contract's checks, then the points go to per-lane strips of K
-//     consecutive points in LDS (stride K + 2: 16-byte aligned) and each lane
-//     reads its strip back into registers.  A partial tile is padded with
-//     points right of and below every valid point, which no test keeps;
-//  2. strip pass 1: maximum y of each strip, x non-decreasing check (the
-//     previous strip's last point comes from the neighbouring lane); wave
+//     consecutive points in LDS (swizzled 16-byte chunks, no padding) and
+//     each lane reads its strip back into registers.  A partial tile is
+//     padded with points right of and below every valid point, which no
+//     test keeps;
+//  2. strip pass 1: x non-decreasing check (the previous strip's last point
+//     comes from the neighbouring lane), maximum y of each strip; wave
 //     prefix and suffix maxima over the strips;
 //  3. exact elimination.  A point r is dropped when some earlier point of
 //     the set is at least as high and some later point is strictly higher:
@@ -304,182 +311,38 @@ __device__ __forceinline__ int wave_min(int v) {
 //     acting as the paper's d1 x d2 thread block;
 //  5. the tile's hood goes to the workspace, or to the output for a
 //     one-tile set.
+// With BOTH, steps 2-5 run a second time on the same registers with every
+// y negated: the lower hood is the upper hood of the mirrored points.  Its
+// results go to the mirrored set (set + lower_sets, slots + lower_n, tile +
+// lower_tiles, group + lower_groups), so the points are read once for both.
+
+// 16-byte chunk c of strip s sits at chunk c ^ tile_swz<K>(s) of the slot,
+// so the transpose writes (8 lanes per strip) and the strip reads (one strip
+// per lane) touch distinct LDS banks.
 template <int K>
-__global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
-                                                  int32_t *cnt_out) {
-  constexpr int S = K;       // a strip's slot in LDS: K points, no padding
-  // 16-byte chunk c of strip s sits at chunk c ^ swz(s) of the slot, so the
-  // transpose writes (8 lanes per strip) and the strip reads (one strip per
-  // lane) touch distinct LDS banks
-  auto swz = [](int strip) { return (strip ^ (strip >> 3)) & (K / 2 - 1); };
-  constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
-  constexpr float PAD_X = 2.0f, PAD_Y = -4.0f;  // right of / below every valid point
-  __shared__ __attribute__((aligned(16))) float2 sxy[64 * S];
-  __shared__ uint16_t sid[64 * S];
-  __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
+__device__ __forceinline__ int tile_swz(int strip) {
+  return (strip ^ (strip >> 3)) & (K / 2 - 1);
+}
 
-  const int tile = blockIdx.x;
-  TileItem it;
-  if (A.one_set) {  // tile t of the only set: no item to fetch
-    it.start = (int64_t)tile * A.tile_len;
-    it.len = (int32_t)min((int64_t)A.tile_len, A.n_total - it.start);
-    it.set = 0;
-    it.rel0 = (int32_t)it.start;
-    it.nb_lo = (int16_t)min(16, it.rel0);
-    it.nb_hi = (int16_t)min((int64_t)16, A.n_total - it.start - it.len);
-    it.final_ = gridDim.x == 1;
-    it.group = it.final_ ? -1 : tile / A.group_fan;
-  } else {
-    it = items[tile];
-  }
+constexpr float TILE_PAD_X = 2.0f, TILE_PAD_Y = -4.0f;  // right of / below every valid point
+
+// Steps 2 (maxima) to 5 of one hood of the tile whose points are p (this
+// lane's strip, in registers) and, transposed, in sxy.  nb_before / nb_after:
+// highest y of the witnesses before / after the tile (-2: none); err: the
+// tile's data status.
+template <int K>
+__device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, int tile,
+                                          int32_t *cnt_out, const float2 (&p)[K],
+                                          float nb_before, float nb_after, int err, bool fe,
+                                          float2 *sxy, uint16_t *sid, int2 *sblk) {
+  constexpr int S = K;
   const int lane = threadIdx.x;
-  const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
-  const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
-  const float2 *src = A.pts + it.start;
-
-  // ---- 1. load.  Every load of the tile is issued before the first wait:
-  // the tile's points, then (unconditionally, at clamped addresses) the
-  // witnesses from the neighbouring tiles of the same set -- the maximum y
-  // of up to 16 points just before the tile and of up to 16 just after it
-  // (lanes 0-15, two points each) -- and the set's point before the tile.
-  float4 v[NV];
-  const bool full = it.len == 64 * K && (((uintptr_t)src) & 15u) == 0;
-  if (full) {
-    // full, 16-byte aligned tile (the common case): no per-element tests
-    const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
-#pragma unroll
-    for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
-  } else {
-    const bool al = (((uintptr_t)src) & 15u) == 0;
-#pragma unroll
-    for (int r = 0; r < NV; ++r) {
-      const int e = 2 * (lane + 64 * r);
-      v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
-      if (e + 1 < it.len) {
-        if (al) {
-          v[r] = *reinterpret_cast<const float4 *>(src + e);
-        } else {
-          const float2 a = src[e], b = src[e + 1];
-          v[r] = make_float4(a.x, a.y, b.x, b.y);
-        }
-      } else if (e < it.len) {
-        const float2 a = src[e];
-        v[r].x = a.x;
-        v[r].y = a.y;
-      }
-    }
-  }
-  float w0, w1;  // this lane's two witness heights (-2: none)
-  {
-    const int64_t wlo = it.start - it.nb_lo, whi = it.start + it.len + it.nb_hi;
-    const int64_t e = lane < 8 ? it.start - 16 + 2 * lane : it.start + it.len + 2 * (lane - 8);
-    const bool ok0 = lane < 16 && (lane < 8 ? e >= wlo : e < whi);
-    const bool ok1 = lane < 16 && (lane < 8 ? e + 1 >= wlo : e + 1 < whi);
-    const float y0 = A.pts[ok0 ? e : it.start].y, y1 = A.pts[ok1 ? e + 1 : it.start].y;
-    w0 = ok0 ? y0 : -2.0f;
-    w1 = ok1 ? y1 : -2.0f;
-  }
-  const float prev_x = A.pts[it.start - (it.rel0 > 0 ? 1 : 0)].x;
-  const float prev_tile_x = validate && it.rel0 > 0 ? prev_x : -1.0f;  // -1: below every valid x
-
-  int err = 0;
-  bool bad = false;  // some check failed, or the quick checks cannot vouch
-  if (full) {
-    if (validate) {
-      // Quick checks that can only err towards `bad`: |y| <= 1 (NaN fails
-      // the grid test instead), y * 2^30 without fraction (the bits of a
-      // zero fraction are zero), x within [0, 1] at the tile's ends (the
-      // strip pass checks x non-decreasing, NaN included), and x on the grid:
-      // if the first x is at least 2^-7, every x is, and float32 spacing
-      // there is at least 2^-30.
-      float ry = 0.0f;
-      uint32_t gy = 0u;
-#pragma unroll
-      for (int r = 0; r < NV; ++r) {
-        ry = fmaxf(ry, fmaxf(__builtin_fabsf(v[r].y), __builtin_fabsf(v[r].w)));
-        gy |= __float_as_uint(__builtin_amdgcn_fractf(v[r].y * 0x1p30f)) |
-              __float_as_uint(__builtin_amdgcn_fractf(v[r].w * 0x1p30f));
-      }
-      const float x_first = readlane(v[0].x, 0), x_last = readlane(v[NV - 1].z, 63);
-      bad = !(ry <= 1.0f) || gy != 0u || !(x_first >= 0.0f) || !(x_last <= 1.0f);
-      if (!(x_first >= 0x1p-7f)) {
-        uint32_t gx = 0u;
-#pragma unroll
-        for (int r = 0; r < NV; ++r)
-          gx |= __float_as_uint(__builtin_amdgcn_fractf(v[r].x * 0x1p30f)) |
-                __float_as_uint(__builtin_amdgcn_fractf(v[r].z * 0x1p30f));
-        bad = bad || gx != 0u;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < NV; ++r) {
-      const int e = 2 * (lane + 64 * r);
-      float4 *d = reinterpret_cast<float4 *>(
-          __builtin_assume_aligned(sxy + (e / K) * S + 2 * (((e % K) >> 1) ^ swz(e / K)), 16));
-      *d = v[r];
-    }
-  } else {
-#pragma unroll
-    for (int r = 0; r < NV; ++r) {
-      const int e = 2 * (lane + 64 * r);
-      if (validate) {
-        if (e < it.len) err = min(err, check_point(make_float2(v[r].x, v[r].y)));
-        if (e + 1 < it.len) err = min(err, check_point(make_float2(v[r].z, v[r].w)));
-      }
-      *reinterpret_cast<float4 *>(sxy + (e / K) * S + 2 * (((e % K) >> 1) ^ swz(e / K))) = v[r];
-    }
-    bad = err != 0;
-  }
-  // witness maxima: over each group of 8 lanes, then read from lanes 0 and 8
-  float nb_before, nb_after;
-  {
-    float wy = fmaxf(w0, w1);
-    wy = fmaxf(wy, dpp<DPP_QUAD_XOR1>(wy, wy));
-    wy = fmaxf(wy, dpp<DPP_QUAD_XOR2>(wy, wy));
-    wy = fmaxf(wy, dpp<DPP_ROW_HALF_MIRROR>(wy, wy));
-    nb_before = readlane(wy, 0);
-    nb_after = readlane(wy, 8);
-  }
-  wave_sync();
-  const int my_len = min(max(it.len - lane * K, 0), K);
   float2 *st = sxy + lane * S;
   uint16_t *sl = sid + lane * S;
-  float2 p[K];
-#pragma unroll
-  for (int k = 0; k < K / 2; ++k) {
-    const float4 q = *reinterpret_cast<const float4 *>(st + 2 * (k ^ swz(lane)));
-    p[2 * k] = make_float2(q.x, q.y);
-    p[2 * k + 1] = make_float2(q.z, q.w);
-  }
-
-  // ---- 2. strip pass 1
   OrientCount oc;
-  float ymax = PAD_Y;
-  {
-    // last point of the previous strip (lane 0: of the previous tile)
-    const float px0 = dpp<DPP_WAVE_SHR1>(prev_tile_x, p[K - 1].x);
-    float px = px0;
-    bool uns = false;
+  float ymax = TILE_PAD_Y;
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      ymax = fmaxf(ymax, p[i].y);
-      uns = uns || !(p[i].x >= px);
-      px = p[i].x;
-    }
-    if (validate && __ballot(bad || uns)) {
-      // something is off in this tile: the exact error codes, point by point
-      err = 0;
-      px = px0;
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        if (i < my_len) {
-          err = min(err, check_point(p[i]));
-          if (p[i].x < px) err = min(err, UH_ERR_UNSORTED);
-          px = p[i].x;
-        }
-      }
-    }
-  }
+  for (int i = 0; i < K; ++i) ymax = fmaxf(ymax, p[i].y);
   const float incp = wave_prefix_max(ymax), incs = wave_suffix_max(ymax);
   {
     // the tile's highest point: a witness for the first merge level
@@ -524,7 +387,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
 #pragma unroll
           for (int rr = 1; rr < SPP; ++rr) L = seg == rr ? Ls[rr] : L;
           const int Lc = L < 0 ? 0 : L;
-          const float2 q = sxy[Lc * S + 2 * ((i >> 1) ^ swz(Lc)) + (i & 1)];
+          const float2 q = sxy[Lc * S + 2 * ((i >> 1) ^ tile_swz<K>(Lc)) + (i & 1)];
           const float2 w = reinterpret_cast<const float2 *>(sblk)[Lc];
           float in_pre, in_post;
           segment_excl_max<K == 32 ? 32 : 16>(q.y, -2.0f, in_pre, in_post);
@@ -644,6 +507,211 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     if (err) atomicMin(&A.set_status[it.set], err);
   }
   flush_wave_stats(A, it.set, oc);
+}
+
+template <int K, bool BOTH>
+__global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
+                                                  int32_t *cnt_out) {
+  constexpr int S = K;       // a strip's slot in LDS: K points, no padding
+  constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
+  constexpr float PAD_X = TILE_PAD_X, PAD_Y = TILE_PAD_Y;
+  __shared__ __attribute__((aligned(16))) float2 sxy[64 * S];
+  __shared__ uint16_t sid[64 * S];
+  __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
+
+  const int tile = blockIdx.x;
+  TileItem it;
+  if (A.one_set) {  // tile t of the only set: no item to fetch
+    it.start = (int64_t)tile * A.tile_len;
+    it.len = (int32_t)min((int64_t)A.tile_len, A.n_points - it.start);
+    it.set = 0;
+    it.rel0 = (int32_t)it.start;
+    it.nb_lo = (int16_t)min(16, it.rel0);
+    it.nb_hi = (int16_t)min((int64_t)16, A.n_points - it.start - it.len);
+    it.final_ = gridDim.x == 1;
+    it.group = it.final_ ? -1 : tile / A.group_fan;
+  } else {
+    it = items[tile];
+  }
+  const int lane = threadIdx.x;
+  const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
+  const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
+  const float2 *src = A.pts + it.start;
+
+  // ---- 1. load.  Every load of the tile is issued before the first wait:
+  // the tile's points, then (unconditionally, at clamped addresses) the
+  // witnesses from the neighbouring tiles of the same set -- the maximum y
+  // of up to 16 points just before the tile and of up to 16 just after it
+  // (lanes 0-15, two points each) -- and the set's point before the tile.
+  float4 v[NV];
+  const bool full = it.len == 64 * K && (((uintptr_t)src) & 15u) == 0;
+  if (full) {
+    // full, 16-byte aligned tile (the common case): no per-element tests
+    const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
+#pragma unroll
+    for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
+  } else {
+    const bool al = (((uintptr_t)src) & 15u) == 0;
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
+      if (e + 1 < it.len) {
+        if (al) {
+          v[r] = *reinterpret_cast<const float4 *>(src + e);
+        } else {
+          const float2 a = src[e], b = src[e + 1];
+          v[r] = make_float4(a.x, a.y, b.x, b.y);
+        }
+      } else if (e < it.len) {
+        const float2 a = src[e];
+        v[r].x = a.x;
+        v[r].y = a.y;
+      }
+    }
+  }
+  float w0, w1;  // this lane's two witness heights (-2: none)
+  float m0 = -2.0f, m1 = -2.0f;  // ... mirrored, for the lower hood
+  {
+    const int64_t wlo = it.start - it.nb_lo, whi = it.start + it.len + it.nb_hi;
+    const int64_t e = lane < 8 ? it.start - 16 + 2 * lane : it.start + it.len + 2 * (lane - 8);
+    const bool ok0 = lane < 16 && (lane < 8 ? e >= wlo : e < whi);
+    const bool ok1 = lane < 16 && (lane < 8 ? e + 1 >= wlo : e + 1 < whi);
+    const float y0 = A.pts[ok0 ? e : it.start].y, y1 = A.pts[ok1 ? e + 1 : it.start].y;
+    w0 = ok0 ? y0 : -2.0f;
+    w1 = ok1 ? y1 : -2.0f;
+    if constexpr (BOTH) {
+      m0 = ok0 ? -y0 : -2.0f;
+      m1 = ok1 ? -y1 : -2.0f;
+    }
+  }
+  const float prev_x = A.pts[it.start - (it.rel0 > 0 ? 1 : 0)].x;
+  const float prev_tile_x = validate && it.rel0 > 0 ? prev_x : -1.0f;  // -1: below every valid x
+
+  int err = 0;
+  bool bad = false;  // some check failed, or the quick checks cannot vouch
+  if (full) {
+    if (validate) {
+      // Quick checks that can only err towards `bad`: |y| <= 1 (NaN fails
+      // the grid test instead), y * 2^30 without fraction (the bits of a
+      // zero fraction are zero), x within [0, 1] at the tile's ends (the
+      // strip pass checks x non-decreasing, NaN included), and x on the grid:
+      // if the first x is at least 2^-7, every x is, and float32 spacing
+      // there is at least 2^-30.
+      float ry = 0.0f;
+      uint32_t gy = 0u;
+#pragma unroll
+      for (int r = 0; r < NV; ++r) {
+        ry = fmaxf(ry, fmaxf(__builtin_fabsf(v[r].y), __builtin_fabsf(v[r].w)));
+        gy |= __float_as_uint(__builtin_amdgcn_fractf(v[r].y * 0x1p30f)) |
+              __float_as_uint(__builtin_amdgcn_fractf(v[r].w * 0x1p30f));
+      }
+      const float x_first = readlane(v[0].x, 0), x_last = readlane(v[NV - 1].z, 63);
+      bad = !(ry <= 1.0f) || gy != 0u || !(x_first >= 0.0f) || !(x_last <= 1.0f);
+      if (!(x_first >= 0x1p-7f)) {
+        uint32_t gx = 0u;
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+          gx |= __float_as_uint(__builtin_amdgcn_fractf(v[r].x * 0x1p30f)) |
+                __float_as_uint(__builtin_amdgcn_fractf(v[r].z * 0x1p30f));
+        bad = bad || gx != 0u;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      float4 *d = reinterpret_cast<float4 *>(__builtin_assume_aligned(
+          sxy + (e / K) * S + 2 * (((e % K) >> 1) ^ tile_swz<K>(e / K)), 16));
+      *d = v[r];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < NV; ++r) {
+      const int e = 2 * (lane + 64 * r);
+      if (validate) {
+        if (e < it.len) err = min(err, check_point(make_float2(v[r].x, v[r].y)));
+        if (e + 1 < it.len) err = min(err, check_point(make_float2(v[r].z, v[r].w)));
+      }
+      *reinterpret_cast<float4 *>(sxy + (e / K) * S + 2 * (((e % K) >> 1) ^ tile_swz<K>(e / K))) =
+          v[r];
+    }
+    bad = err != 0;
+  }
+  // witness maxima: over each group of 8 lanes, then read from lanes 0 and 8
+  float nb_before, nb_after, mb_before = -2.0f, mb_after = -2.0f;
+  {
+    float wy = fmaxf(w0, w1);
+    wy = fmaxf(wy, dpp<DPP_QUAD_XOR1>(wy, wy));
+    wy = fmaxf(wy, dpp<DPP_QUAD_XOR2>(wy, wy));
+    wy = fmaxf(wy, dpp<DPP_ROW_HALF_MIRROR>(wy, wy));
+    nb_before = readlane(wy, 0);
+    nb_after = readlane(wy, 8);
+    if constexpr (BOTH) {
+      float my = fmaxf(m0, m1);
+      my = fmaxf(my, dpp<DPP_QUAD_XOR1>(my, my));
+      my = fmaxf(my, dpp<DPP_QUAD_XOR2>(my, my));
+      my = fmaxf(my, dpp<DPP_ROW_HALF_MIRROR>(my, my));
+      mb_before = readlane(my, 0);
+      mb_after = readlane(my, 8);
+    }
+  }
+  wave_sync();
+  const int my_len = min(max(it.len - lane * K, 0), K);
+  float2 *st = sxy + lane * S;
+  float2 p[K];
+#pragma unroll
+  for (int k = 0; k < K / 2; ++k) {
+    const float4 q = *reinterpret_cast<const float4 *>(st + 2 * (k ^ tile_swz<K>(lane)));
+    p[2 * k] = make_float2(q.x, q.y);
+    p[2 * k + 1] = make_float2(q.z, q.w);
+  }
+
+  // ---- 2. strip pass 1: x order (the last point of the previous strip;
+  // lane 0: of the previous tile)
+  {
+    const float px0 = dpp<DPP_WAVE_SHR1>(prev_tile_x, p[K - 1].x);
+    float px = px0;
+    bool uns = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      uns = uns || !(p[i].x >= px);
+      px = p[i].x;
+    }
+    if (validate && __ballot(bad || uns)) {
+      // something is off in this tile: the exact error codes, point by point
+      err = 0;
+      px = px0;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        if (i < my_len) {
+          err = min(err, check_point(p[i]));
+          if (p[i].x < px) err = min(err, UH_ERR_UNSORTED);
+          px = p[i].x;
+        }
+      }
+    }
+  }
+  tile_hood<K>(A, it, tile, cnt_out, p, nb_before, nb_after, err, fe, sxy, sid, sblk);
+
+  if constexpr (BOTH) {
+    // the lower hood: the same points mirrored in the x axis (the padding
+    // stays below every valid point), back in their LDS strips
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if (i < my_len) p[i].y = -p[i].y;
+    wave_sync();  // every lane is done with the upper hood's LDS
+#pragma unroll
+    for (int k = 0; k < K / 2; ++k)
+      *reinterpret_cast<float4 *>(st + 2 * (k ^ tile_swz<K>(lane))) =
+          make_float4(p[2 * k].x, p[2 * k].y, p[2 * k + 1].x, p[2 * k + 1].y);
+    wave_sync();
+    TileItem lo = it;
+    lo.start += A.lower_n;
+    lo.set += A.lower_sets;
+    if (lo.group >= 0) lo.group += A.lower_groups;
+    tile_hood<K>(A, lo, tile + A.lower_tiles, cnt_out, p, mb_before, mb_after, err, fe, sxy,
+                 sid, sblk);
+  }
 }
 
 // ---------------------------------------------------------------- merges
@@ -1040,6 +1108,32 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   flush_wave_stats(A, it.set, oc);
 }
 
+// ------------------------------------------------------------ convex hull
+// Joins the two hoods of one set into its convex hull, counter-clockwise:
+// the lower hood left to right, then the upper hood right to left without
+// the corners the two share at either end.  hood: upper hood at [0, n),
+// lower at [n, 2n); cnt: their counts (or the set's data-error status).
+__global__ void hull_assemble_kernel(const int32_t *hood, const int32_t *cnt, int64_t n,
+                                     int32_t *out_idx, int32_t *out_count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cnt[0] <= 0 || cnt[1] <= 0) {  // an empty set, or a data error (reported by both hoods)
+    if (t == 0) *out_count = min(cnt[0], cnt[1]);
+    return;
+  }
+  // a hood never has more than n corners, nor the hull (every index at most
+  // once); the clamps only keep the accesses inside the buffers
+  const int32_t hu = (int32_t)min((int64_t)cnt[0], n), hl = (int32_t)min((int64_t)cnt[1], n);
+  const int32_t *up = hood, *lo = hood + n;
+  const bool skip_right = up[hu - 1] == lo[hl - 1];
+  const int32_t k_hi = hu - 1 - (skip_right ? 1 : 0);  // upper corners kept: k_hi down to k_lo
+  const int32_t k_lo = up[0] == lo[0] ? 1 : 0;
+  const int32_t nup = k_hi >= k_lo ? k_hi - k_lo + 1 : 0;
+  const int64_t total = min((int64_t)hl + nup, n);
+  for (int64_t e = t; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    out_idx[e] = e < hl ? lo[e] : up[k_hi - (e - hl)];
+  if (t == 0) *out_count = (int32_t)total;
+}
+
 // ---------------------------------------------------------------- probes
 __global__ void bridge_kernel(const float2 *P, int hp, const float2 *Q, int hq,
                               int L, int32_t *out_ab) {
@@ -1073,6 +1167,9 @@ struct upper_hull_plan {
   int64_t N = 0;
   int K = 16, T = 4096, F = 256;
   uint32_t flags = 0;
+  bool both = false;       // upper and lower hood: S, N, ntiles, ngroups count both
+  int32_t in_S = 0;        // input sets
+  int64_t in_N = 0;        // input points
   int32_t ntiles = 0;
   bool has_empty = false;  // some set has no points
   int32_t ngroups = 0;     // first-level merge items
@@ -1093,6 +1190,7 @@ struct upper_hull_plan {
   std::map<std::tuple<const void *, void *, void *, void *>, hipGraphExec_t> graphs;
   hipStream_t cap_stream = nullptr;
   hipEvent_t probe_before = nullptr, probe_after = nullptr;
+  int32_t *hull_idx = nullptr, *hull_cnt = nullptr;  // convex_hull: both hoods before joining
   std::mutex mu;
 };
 
@@ -1127,6 +1225,8 @@ void free_plan_memory(upper_hull_plan *p) {
   hipFree(p->set_status);
   hipFree(p->tile_max);
   hipFree(p->group_max);
+  hipFree(p->hull_idx);
+  hipFree(p->hull_cnt);
   for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
 }
@@ -1140,16 +1240,24 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
     hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, stream, p->S, A);
   }
   if (p->ntiles > 0) {
-    const dim3 grid(p->ntiles), blk(64);
+    // with both hoods, one wave per input tile computes both of its hoods
+    const dim3 grid(p->both ? p->ntiles / 2 : p->ntiles), blk(64);
     if (p->probe_before && hipEventRecord(p->probe_before, stream) != hipSuccess)
       return UH_ERR_HIP;
-    switch (p->K) {
-      case 4: hipLaunchKernelGGL(tile_kernel<4>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
-      case 8: hipLaunchKernelGGL(tile_kernel<8>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
-      case 16: hipLaunchKernelGGL(tile_kernel<16>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
-      case 32: hipLaunchKernelGGL(tile_kernel<32>, grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0); break;
+#define UH_TILE(KK, BB) \
+  hipLaunchKernelGGL((tile_kernel<KK, BB>), grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0)
+    switch (p->K * 2 + (p->both ? 1 : 0)) {
+      case 8: UH_TILE(4, false); break;
+      case 9: UH_TILE(4, true); break;
+      case 16: UH_TILE(8, false); break;
+      case 17: UH_TILE(8, true); break;
+      case 32: UH_TILE(16, false); break;
+      case 33: UH_TILE(16, true); break;
+      case 64: UH_TILE(32, false); break;
+      case 65: UH_TILE(32, true); break;
       default: return UH_ERR_ARG;
     }
+#undef UH_TILE
     if (p->probe_after && hipEventRecord(p->probe_after, stream) != hipSuccess)
       return UH_ERR_HIP;
   }
@@ -1166,7 +1274,41 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
 }
 
 std::mutex g_cache_mu;
-std::map<std::pair<int, int64_t>, upper_hull_plan *> g_single_plans;
+std::map<std::tuple<int, int64_t, uint32_t>, upper_hull_plan *> g_single_plans;
+
+// The cached single-set plan for n points on the current device (flags:
+// UH_FLAG_BOTH_HOODS for the convex hull, which also gets its buffers).
+int single_plan(int64_t n, uint32_t flags, hipStream_t stream, upper_hull_plan **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto key = std::make_tuple(dev, n, flags);
+  auto it = g_single_plans.find(key);
+  if (it != g_single_plans.end()) {
+    *out = it->second;
+    return UH_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
+  if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
+  if (g_single_plans.size() >= 8) {  // bounded cache: drop the oldest
+    upper_hull_plan_destroy(g_single_plans.begin()->second);
+    g_single_plans.erase(g_single_plans.begin());
+  }
+  const int64_t off[2] = {0, n};
+  const upper_hull_config cfg = {0, 0, flags};
+  upper_hull_plan *p = nullptr;
+  int rc = upper_hull_plan_create(off, 1, &cfg, &p);
+  if (!rc && (flags & UH_FLAG_BOTH_HOODS)) {
+    rc = dalloc(&p->hull_idx, (size_t)(2 * n));
+    rc = rc ? rc : dalloc(&p->hull_cnt, 2);
+    if (rc) upper_hull_plan_destroy(p);
+  }
+  if (rc) return rc;
+  g_single_plans.emplace(key, p);
+  *out = p;
+  return UH_OK;
+}
 
 }  // namespace
 
@@ -1206,10 +1348,22 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
   if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
 
+  // With both hoods the schedule covers 2 * num_sets sets over 2 * N slots:
+  // set num_sets + s is the lower hood of set s (the mirrored points), its
+  // slots and outputs N further on.  Its tiles and groups mirror those of
+  // set s, since sets are laid out in order and the two halves are alike.
+  const bool both = (flags & UH_FLAG_BOTH_HOODS) != 0;
+  const int32_t VS = both ? 2 * num_sets : num_sets;
+  std::vector<int64_t> voff(set_offsets, set_offsets + num_sets + 1);
+  if (both)
+    for (int32_t s = 0; s < num_sets; ++s) voff.push_back(set_offsets[num_sets] + set_offsets[s + 1]);
   auto *p = new upper_hull_plan();
   hipGetDevice(&p->device);
-  p->S = num_sets;
-  p->N = set_offsets[num_sets];
+  p->both = both;
+  p->in_S = num_sets;
+  p->in_N = set_offsets[num_sets];
+  p->S = VS;
+  p->N = voff[VS];
   p->K = K;
   p->T = 64 * K;
   p->F = F;
@@ -1217,15 +1371,15 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
 
   // level 0: tiles; then merge passes of fan-in F until one hood per set
   std::vector<TileItem> tiles;
-  std::vector<int32_t> first(num_sets), count(num_sets);  // blocks per set
-  for (int32_t s = 0; s < num_sets; ++s) {
-    const int64_t n = set_offsets[s + 1] - set_offsets[s];
+  std::vector<int32_t> first(VS), count(VS);  // blocks per set
+  for (int32_t s = 0; s < VS; ++s) {
+    const int64_t n = voff[s + 1] - voff[s];
     const int64_t nt = (n + p->T - 1) / p->T;
     first[s] = (int32_t)tiles.size();
     count[s] = (int32_t)nt;
     for (int64_t t = 0; t < nt; ++t) {
       TileItem it;
-      it.start = set_offsets[s] + t * p->T;
+      it.start = voff[s] + t * p->T;
       it.len = (int32_t)std::min<int64_t>(p->T, n - t * p->T);
       it.set = s;
       it.rel0 = (int32_t)(t * p->T);
@@ -1237,21 +1391,21 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     }
   }
   p->ntiles = (int32_t)tiles.size();
-  for (int32_t s = 0; s < num_sets; ++s) p->has_empty = p->has_empty || set_offsets[s + 1] == set_offsets[s];
+  for (int32_t s = 0; s < VS; ++s) p->has_empty = p->has_empty || voff[s + 1] == voff[s];
   // Within a set the blocks of a level are consecutive and equally long
   // (except the last), so child k of an item starts at off + k * stride.
   std::vector<std::vector<MergeItem>> passes;
-  std::vector<int32_t> g0(num_sets, 0), ng(num_sets, 0), fs0(num_sets, F);  // first level per set
+  std::vector<int32_t> g0(VS, 0), ng(VS, 0), fs0(VS, F);  // first level per set
   int64_t stride = p->T;
   for (;;) {
     std::vector<MergeItem> items;
-    std::vector<int32_t> nfirst(num_sets), ncount(num_sets);
+    std::vector<int32_t> nfirst(VS), ncount(VS);
     // With the default fan-in, a set with BLOCK + 1 .. WIDE blocks left can
     // finish in one wide workgroup (one per CU), if few sets need one.
     int32_t nwide = 0;
-    for (int32_t s = 0; s < num_sets; ++s) nwide += F == BLOCK && count[s] > BLOCK && count[s] <= WIDE;
+    for (int32_t s = 0; s < VS; ++s) nwide += F == BLOCK && count[s] > BLOCK && count[s] <= WIDE;
     const bool use_wide = nwide > 0 && nwide <= 256;
-    for (int32_t s = 0; s < num_sets; ++s) {
+    for (int32_t s = 0; s < VS; ++s) {
       nfirst[s] = (int32_t)items.size();
       ncount[s] = 0;
       if (count[s] <= 1) continue;
@@ -1261,7 +1415,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
         MergeItem m;
         m.child0 = first[s] + i * FS;
         m.nch = std::min(FS, count[s] - i * FS);
-        m.off = set_offsets[s] + (int64_t)i * FS * stride;
+        m.off = voff[s] + (int64_t)i * FS * stride;
         m.stride = stride;
         m.set = s;
         m.final_ = nitems == 1;
@@ -1281,7 +1435,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     stride *= F;
     first = nfirst;
     // sets finished in this pass keep count 1 -> no further items
-    for (int32_t s = 0; s < num_sets; ++s) count[s] = ncount[s];
+    for (int32_t s = 0; s < VS; ++s) count[s] = ncount[s];
   }
 
   // groups: the first-level items; every item knows its set's groups, and
@@ -1291,8 +1445,8 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       m.g0 = g0[m.set];
       m.ng = ng[m.set];
     }
-  for (int32_t s = 0, t0 = 0; s < num_sets; ++s) {
-    const int64_t n = set_offsets[s + 1] - set_offsets[s];
+  for (int32_t s = 0, t0 = 0; s < VS; ++s) {
+    const int64_t n = voff[s + 1] - voff[s];
     const int32_t nt = (int32_t)((n + p->T - 1) / p->T);
     if (nt > 1)
       for (int32_t t = 0; t < nt; ++t) tiles[t0 + t].group = g0[s] + t / fs0[s];
@@ -1300,8 +1454,25 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   }
   p->group_fan = fs0[0];
   p->ngroups = passes.empty() ? 0 : (int32_t)passes[0].size();
+  if (both) {
+    // the tile kernel derives each lower tile from its upper twin: check that
+    // the schedule's second half is the first half moved by (N, S, tiles/2,
+    // groups/2), which holds because the two halves have the same set sizes
+    const int32_t ht = p->ntiles / 2, hg = p->ngroups / 2;
+    bool ok = p->ntiles % 2 == 0 && p->ngroups % 2 == 0;
+    for (int32_t t = 0; ok && t < ht; ++t) {
+      const TileItem &a = tiles[t], &b = tiles[t + ht];
+      ok = b.start == a.start + p->in_N && b.len == a.len && b.set == a.set + num_sets &&
+           b.rel0 == a.rel0 && b.nb_lo == a.nb_lo && b.nb_hi == a.nb_hi &&
+           b.final_ == a.final_ && b.group == (a.group < 0 ? -1 : a.group + hg);
+    }
+    if (!ok) {
+      delete p;
+      return UH_ERR_ARG;
+    }
+  }
   int rc = UH_OK;
-  std::vector<int64_t> so(set_offsets, set_offsets + num_sets + 1);
+  std::vector<int64_t> so(voff.begin(), voff.end());
   rc = rc ? rc : dalloc(&p->d_set_start, so.size());
   rc = rc ? rc : upload(p->d_set_start, so);
   rc = rc ? rc : dalloc(&p->d_tiles, tiles.size());
@@ -1325,14 +1496,14 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   rc = rc ? rc : dalloc(&p->ws_idx, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws2_xy, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws2_idx, (size_t)p->N);
-  rc = rc ? rc : dalloc(&p->set_status, (size_t)num_sets);
+  rc = rc ? rc : dalloc(&p->set_status, (size_t)VS);
   rc = rc ? rc : dalloc(&p->tile_max, (size_t)p->ntiles);
   rc = rc ? rc : dalloc(&p->group_max, (size_t)p->ngroups * GROUP_STRIDE);
   if (!rc && p->ngroups > 0 &&
       hipMemset(p->group_max, 0, (size_t)p->ngroups * GROUP_STRIDE * sizeof(uint32_t)) !=
           hipSuccess)
     rc = UH_ERR_HIP;
-  if (!rc && hipMemset(p->set_status, 0, (size_t)num_sets * sizeof(int32_t)) != hipSuccess)
+  if (!rc && hipMemset(p->set_status, 0, (size_t)VS * sizeof(int32_t)) != hipSuccess)
     rc = UH_ERR_HIP;
   if (rc) {
     free_plan_memory(p);
@@ -1377,8 +1548,13 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   A.group_fan = p->group_fan;
   A.tile_max = p->tile_max;
   A.group_max = p->group_max;
-  A.one_set = p->S == 1;
+  A.one_set = p->in_S == 1;
   A.flags = p->flags;
+  A.n_points = p->in_N;
+  A.lower_n = p->both ? p->in_N : 0;
+  A.lower_tiles = p->both ? p->ntiles / 2 : 0;
+  A.lower_groups = p->both ? p->ngroups / 2 : 0;
+  A.lower_sets = p->both ? p->in_S : 0;
   if (!(p->flags & UH_FLAG_GRAPH)) return enqueue_run(p, A, stream);
 
   std::lock_guard<std::mutex> lock(p->mu);
@@ -1421,30 +1597,26 @@ int upper_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_co
                hipStream_t stream) {
   if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx)))
     return UH_ERR_ARG;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
   upper_hull_plan *p = nullptr;
-  {
-    std::lock_guard<std::mutex> lock(g_cache_mu);
-    auto key = std::make_pair(dev, n);
-    auto it = g_single_plans.find(key);
-    if (it != g_single_plans.end()) {
-      p = it->second;
-    } else {
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
-      if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
-      if (g_single_plans.size() >= 8) {  // bounded cache: drop the oldest
-        upper_hull_plan_destroy(g_single_plans.begin()->second);
-        g_single_plans.erase(g_single_plans.begin());
-      }
-      const int64_t off[2] = {0, n};
-      const int rc = upper_hull_plan_create(off, 1, nullptr, &p);
-      if (rc) return rc;
-      g_single_plans.emplace(key, p);
-    }
-  }
+  const int rc = single_plan(n, 0u, stream, &p);
+  if (rc) return rc;
   return upper_hull_plan_run(p, points, out_idx, out_count, nullptr, stream);
+}
+
+int convex_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_count,
+                hipStream_t stream) {
+  if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx)))
+    return UH_ERR_ARG;
+  upper_hull_plan *p = nullptr;
+  int rc = single_plan(n, UH_FLAG_BOTH_HOODS, stream, &p);
+  if (rc) return rc;
+  // both hoods into the plan's buffers, then one join pass into out_idx
+  rc = upper_hull_plan_run(p, points, p->hull_idx, p->hull_cnt, nullptr, stream);
+  if (rc) return rc;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(hull_assemble_kernel, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256),
+                     0, stream, p->hull_idx, p->hull_cnt, n, out_idx, out_count);
+  return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
 
 int upper_hull_autotune(const float *points, const int64_t *set_offsets,
@@ -1460,8 +1632,9 @@ int upper_hull_autotune(const float *points, const int64_t *set_offsets,
   flags &= ~UH_FLAG_GRAPH;
   int32_t *out_idx = nullptr, *out_counts = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = dalloc(&out_idx, (size_t)std::max<int64_t>(N, 1));
-  rc = rc ? rc : dalloc(&out_counts, (size_t)num_sets);
+  const int h = (flags & UH_FLAG_BOTH_HOODS) ? 2 : 1;  // hoods per set
+  int rc = dalloc(&out_idx, (size_t)std::max<int64_t>(h * N, 1));
+  rc = rc ? rc : dalloc(&out_counts, (size_t)(h * num_sets));
   if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = UH_ERR_HIP;
   float best_t = -1.0f;

@@ -15,7 +15,7 @@ HEADER = os.path.join(ROOT, "include", "wagener_hull.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(upper_hull\w*)\s*\(", text, flags=re.M)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b((?:upper|convex)_hull\w*)\s*\(", text, flags=re.M)
     return sorted(set(names))
 
 
@@ -23,7 +23,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("upper_hull", "upper_hull_plan_create", "upper_hull_plan_run",
                      "upper_hull_plan_destroy", "upper_hull_bridge", "upper_hull_orient",
-                     "upper_hull_status_string"):
+                     "upper_hull_status_string", "convex_hull"):
         assert required in names
     assert sorted(names) == sorted(uh.EXPORTS)
 
