@@ -84,13 +84,20 @@ class HipEvents:
         self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def cpu_baseline(pts_np, off, budget_s: float):
+def cpu_baseline(pts_np, off, budget_s: float, both: bool = False):
+    """The oracle over the whole workload, repeated until budget_s; with both,
+    the upper and the lower hood of every set (outputs laid out as the
+    library's two halves)."""
+    import numpy as np
     import oracle
     t_total, reps = 0.0, 0
     out = cnt = None
     while reps < 1 or t_total < budget_s:
         t0 = time.perf_counter()
         out, cnt = oracle.upper_hull_batched(pts_np, off)
+        if both:
+            lo, lcnt = oracle.lower_hull_batched(pts_np, off)
+            out, cnt = np.concatenate([out[:len(pts_np)], lo]), np.concatenate([cnt, lcnt])
         t_total += time.perf_counter() - t0
         reps += 1
     return len(pts_np) * reps / t_total, reps, t_total, out, cnt
@@ -116,6 +123,9 @@ def main():
     ap.add_argument("--read-reference", action="store_true",
                     help="also time the library's plain streaming read of the same input: the "
                          "bandwidth a simple read reaches on this GPU")
+    ap.add_argument("--both-hoods", action="store_true",
+                    help="upper and lower hood of every set from the same read (the convex "
+                         "hull's two halves)")
     ap.add_argument("--flush", action="store_true",
                     help="cold caches: overwrite a 1 GiB buffer before every timed step (outside "
                          "the step's own events), so the input is read from HBM, not the 256 MB "
@@ -156,7 +166,9 @@ def main():
     pts = torch.from_numpy(pts_np).to(dev)
     N, S = len(pts_np), len(off) - 1
     flags = (uh.UH_FLAG_GRAPH if args.graph else 0) | \
-        (uh.UH_FLAG_FORCE_FALLBACK if args.force_fallback else 0)
+        (uh.UH_FLAG_FORCE_FALLBACK if args.force_fallback else 0) | \
+        (uh.UH_FLAG_BOTH_HOODS if args.both_hoods else 0)
+    H = 2 if args.both_hoods else 1  # hoods per set
     fan_in = 0
     tuned = None
     if args.autotune:
@@ -167,9 +179,9 @@ def main():
                  "seconds": round(time.perf_counter() - t0, 1)}
         log(f"[bench] autotune: strip {args.strip}, fan-in {fan_in} ({tms:.3f} ms)")
     plan = uh.upper_hull_plan_create(off, strip=args.strip, fan_in=fan_in, flags=flags)
-    out_idx = torch.empty(max(N, 1), dtype=torch.int32, device=dev)
-    out_cnt = torch.empty(S, dtype=torch.int32, device=dev)
-    stats = torch.zeros((S, 2), dtype=torch.int64, device=dev)
+    out_idx = torch.empty(max(H * N, 1), dtype=torch.int32, device=dev)
+    out_cnt = torch.empty(H * S, dtype=torch.int32, device=dev)
+    stats = torch.zeros((H * S, 2), dtype=torch.int64, device=dev)
 
     ev = HipEvents()
     probes = []
@@ -234,10 +246,18 @@ def main():
     plain = None
     if args.compare_plain:
         log(f"[bench] plain per-set method: {S} plans ...")
-        plans = [uh.upper_hull_plan_create([0, int(off[s + 1] - off[s])], strip=args.strip)
-                 for s in range(S)]
-        views = [(pts[off[s]:off[s + 1]], out_idx[off[s]:max(off[s + 1], off[s] + 1)],
-                  out_cnt[s:s + 1]) for s in range(S)]
+        pflags = flags & uh.UH_FLAG_BOTH_HOODS
+        plans = [uh.upper_hull_plan_create([0, int(off[s + 1] - off[s])], strip=args.strip,
+                                           flags=pflags) for s in range(S)]
+        scratch_idx = torch.empty(max(H * int(np.max(np.diff(off))), 1), dtype=torch.int32,
+                                  device=dev)
+        scratch_cnt = torch.empty(H * S, dtype=torch.int32, device=dev)
+        if H == 1:
+            views = [(pts[off[s]:off[s + 1]], out_idx[off[s]:max(off[s + 1], off[s] + 1)],
+                      out_cnt[s:s + 1]) for s in range(S)]
+        else:  # both hoods of each set into scratch; the counts are compared below
+            views = [(pts[off[s]:off[s + 1]], scratch_idx, scratch_cnt[H * s:H * s + H])
+                     for s in range(S)]
         for s in range(S):  # warm-up
             plans[s].run(*views[s])
         torch.cuda.synchronize()
@@ -251,7 +271,12 @@ def main():
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / reps
         gpu_ms = start.elapsed_time(end) / reps
-        plain_ok = bool(np.array_equal(out_cnt.cpu().numpy(), cnt_np))
+        if H == 1:
+            plain_ok = bool(np.array_equal(out_cnt.cpu().numpy(), cnt_np))
+        else:
+            sc = scratch_cnt.cpu().numpy().reshape(S, 2)
+            plain_ok = bool(np.array_equal(sc[:, 0], cnt_np[:S]) and
+                            np.array_equal(sc[:, 1], cnt_np[S:]))
         for pl in plans:
             pl.close()
         plain = {"ms_per_step": round(gpu_ms, 3), "host_wall_ms_per_step": round(wall * 1e3, 3),
@@ -271,7 +296,7 @@ def main():
     roofline = None
     if tile_ms:
         achieved = alg_tile / (tile_ms * 1e-3) / 1e9
-        traffic = load_traffic(args.workload, args.strip)
+        traffic = None if args.both_hoods else load_traffic(args.workload, args.strip)
         roofline = {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -283,14 +308,16 @@ def main():
     checked = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
-        rate, reps, secs, ref_out, ref_cnt = cpu_baseline(pts_np, off, args.cpu_budget)
+        rate, reps, secs, ref_out, ref_cnt = cpu_baseline(pts_np, off, args.cpu_budget,
+                                                          both=args.both_hoods)
         cpu = {"value": round(rate, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-               "sample": f"whole workload ({N} points, {S} sets), {reps} run(s), "
+               "sample": f"whole workload ({N} points, {S} sets"
+                         f"{', both hoods' if H == 2 else ''}), {reps} run(s), "
                          f"{secs:.1f} s, single thread"}
         got = out_idx.cpu().numpy()
+        voff = np.concatenate([off[:-1] + h * N for h in range(H)])  # start of every output set
         checked = bool(np.array_equal(cnt_np, ref_cnt.astype(np.int32)) and all(
-            np.array_equal(got[off[s]:off[s] + cnt_np[s]], ref_out[off[s]:off[s] + cnt_np[s]])
-            for s in range(S)))
+            np.array_equal(got[a:a + c], ref_out[a:a + c]) for a, c in zip(voff, cnt_np)))
         log(f"[bench] oracle {rate:.4g} points/s; GPU result equals oracle: {checked}")
 
     line = {
@@ -303,6 +330,7 @@ def main():
                    "fan_in": fan_in or 256, "autotuned": tuned,
                    "graph": bool(args.graph), "force_fallback": bool(args.force_fallback),
                    "cold_cache": bool(args.flush),
+                   "hoods": "upper and lower" if H == 2 else "upper",
                    "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),
                    "fallback_rate": (fallbacks / evals) if evals else 0.0,

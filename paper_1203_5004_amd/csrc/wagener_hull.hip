@@ -65,7 +65,8 @@ struct TileItem {    // one tile of the tile pass (everything a tile needs: 32 b
   int32_t rel0;      // start minus the set's start (set-relative index of the first point)
   int16_t nb_lo;     // points of the set just before the tile used as witnesses, 0 .. 16
   int16_t nb_hi;     // points of the set just after it used as witnesses, 0 .. 16
-  int32_t final_;    // 1 if this tile is its set's only tile
+  int32_t set_len;   // points in the tile's set (the tile is the set's only one iff
+                     // rel0 == 0 and len == set_len)
   int32_t group;     // the first-level merge item that takes this tile (-1: none)
 };
 
@@ -333,10 +334,12 @@ constexpr float TILE_PAD_X = 2.0f, TILE_PAD_Y = -4.0f;  // right of / below ever
 template <int K>
 __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, int tile,
                                           int32_t *cnt_out, const float2 (&p)[K],
-                                          float nb_before, float nb_after, int err, bool fe,
+                                          float nb_before, float nb_after, float2 set_first,
+                                          float2 set_last, int err, bool fe,
                                           float2 *sxy, uint16_t *sid, int2 *sblk) {
   constexpr int S = K;
   const int lane = threadIdx.x;
+  const bool fin = it.rel0 == 0 && it.len == it.set_len;  // the set's only tile
   float2 *st = sxy + lane * S;
   uint16_t *sl = sid + lane * S;
   OrientCount oc;
@@ -357,7 +360,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
   const int rel0 = it.rel0;
 
   // ---- 3. elimination; few survivors leave as a point list
-  if ((K == 16 || K == 32) && !it.final_) {
+  if ((K == 16 || K == 32) && !fin) {
     constexpr int SPP = 64 / K;  // candidate strips per pass
     const uint64_t cand = __ballot(ymax > exp_pre || ymax >= exp_suf);
     const int ncand = __builtin_popcountll(cand);
@@ -427,8 +430,39 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
       bm = fmaxf(bm, p[i].y);
     }
   }
-  if constexpr (K != 16 && K != 32) {
-    // survivor list for the other strip widths: ranks by a wave prefix sum
+  // Chord tests: a point strictly between two points a and b of its set in x
+  // that lies on or below the segment a b is no corner (the hood's
+  // definition).  They catch what the height test above cannot: the points
+  // of a convex arm, and the lower hood of an arch.  Pairs: the set's first
+  // and last points, then the tile's.  Each is worth its orientation tests
+  // only where strips lie below it: each lane first estimates (in plain
+  // float32, a guess that decides nothing but whether to test) on which side
+  // the first point of its strip lies, and the tile runs the exact test if
+  // 48 lanes find theirs below (not on the noise of a nearly straight run).
+  bool chord_ran = false;
+  {
+    const int ll = it.len - 1, lane_l = ll / K, il = ll % K;
+    const float2 tf = make_float2(readlane(p[0].x, 0), readlane(p[0].y, 0));
+    const float2 tl = sxy[lane_l * S + 2 * ((il >> 1) ^ tile_swz<K>(lane_l)) + (il & 1)];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const float2 f = c == 0 ? set_first : tf, l = c == 0 ? set_last : tl;
+      const float est = (l.x - f.x) * (p[0].y - f.y) - (l.y - f.y) * (p[0].x - f.x);
+      const bool below0 = lane * K < it.len && est < 0.0f;
+      if (__builtin_popcountll(__ballot(below0)) >= 48) {
+        chord_ran = true;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+          if (((keep >> i) & 1u) && f.x < p[i].x && p[i].x < l.x &&
+              orient_sign(f, l, p[i], oc, fe) <= 0)
+            keep &= ~(1u << i);
+      }
+    }
+  }
+  if ((K != 16 && K != 32) || chord_ran) {
+    // few survivors leave as a sorted point list: ranks by a wave prefix sum
+    // (with strips of 16 or 32 the height test's survivors were counted
+    // already; only the chord tests can have left few)
     const int nk = __builtin_popcount(keep);
     int koff = nk;
     for (int o = 1; o < 64; o <<= 1) {
@@ -437,7 +471,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     }
     const int nsurv = __shfl(koff, 63, 64);
     koff -= nk;
-    if (!it.final_ && nsurv <= TILE_LIST_MAX) {
+    if (!fin && nsurv <= TILE_LIST_MAX) {
       int r = koff;
 #pragma unroll
       for (int i = 0; i < K; ++i) {
@@ -449,6 +483,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
       }
       if (lane == 0) cnt_out[tile] = (int)((uint32_t)nsurv | POINTS_FLAG);
       if (err) atomicMin(&A.set_status[it.set], err);
+      flush_wave_stats(A, it.set, oc);
       return;
     }
   }
@@ -493,7 +528,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
 
   // ---- 5. output
   const int hb = nleaf ? sblk[0].x : 0, hc = nleaf ? sblk[0].y : 0;
-  if (it.final_) {
+  if (fin) {
     if (__ballot(err != 0)) err = wave_min(err);
     int32_t *dst = A.out_idx + (it.start - it.rel0);
     for (int k = lane; k < hc; k += 64) dst[k] = rel0 + (int)sid[hb + k];
@@ -528,8 +563,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     it.rel0 = (int32_t)it.start;
     it.nb_lo = (int16_t)min(16, it.rel0);
     it.nb_hi = (int16_t)min((int64_t)16, A.n_points - it.start - it.len);
-    it.final_ = gridDim.x == 1;
-    it.group = it.final_ ? -1 : tile / A.group_fan;
+    it.set_len = (int32_t)A.n_points;
+    it.group = gridDim.x == 1 ? -1 : tile / A.group_fan;
   } else {
     it = items[tile];
   }
@@ -585,6 +620,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       m1 = ok1 ? -y1 : -2.0f;
     }
   }
+  const int64_t set0 = it.start - it.rel0;
+  float2 set_first = A.pts[set0], set_last = A.pts[set0 + it.set_len - 1];  // chord of the set
   const float prev_x = A.pts[it.start - (it.rel0 > 0 ? 1 : 0)].x;
   const float prev_tile_x = validate && it.rel0 > 0 ? prev_x : -1.0f;  // -1: below every valid x
 
@@ -691,7 +728,8 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
       }
     }
   }
-  tile_hood<K>(A, it, tile, cnt_out, p, nb_before, nb_after, err, fe, sxy, sid, sblk);
+  tile_hood<K>(A, it, tile, cnt_out, p, nb_before, nb_after, set_first, set_last, err, fe, sxy,
+               sid, sblk);
 
   if constexpr (BOTH) {
     // the lower hood: the same points mirrored in the x axis (the padding
@@ -709,8 +747,10 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     lo.start += A.lower_n;
     lo.set += A.lower_sets;
     if (lo.group >= 0) lo.group += A.lower_groups;
-    tile_hood<K>(A, lo, tile + A.lower_tiles, cnt_out, p, mb_before, mb_after, err, fe, sxy,
-                 sid, sblk);
+    set_first.y = -set_first.y;
+    set_last.y = -set_last.y;
+    tile_hood<K>(A, lo, tile + A.lower_tiles, cnt_out, p, mb_before, mb_after, set_first,
+                 set_last, err, fe, sxy, sid, sblk);
   }
 }
 
@@ -1385,7 +1425,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       it.rel0 = (int32_t)(t * p->T);
       it.nb_lo = (int16_t)std::min<int64_t>(16, t * p->T);
       it.nb_hi = (int16_t)std::min<int64_t>(16, n - t * p->T - it.len);
-      it.final_ = nt == 1;
+      it.set_len = (int32_t)n;
       it.group = -1;  // set below, once the first merge level is known
       tiles.push_back(it);
     }
@@ -1464,7 +1504,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       const TileItem &a = tiles[t], &b = tiles[t + ht];
       ok = b.start == a.start + p->in_N && b.len == a.len && b.set == a.set + num_sets &&
            b.rel0 == a.rel0 && b.nb_lo == a.nb_lo && b.nb_hi == a.nb_hi &&
-           b.final_ == a.final_ && b.group == (a.group < 0 ? -1 : a.group + hg);
+           b.set_len == a.set_len && b.group == (a.group < 0 ? -1 : a.group + hg);
     }
     if (!ok) {
       delete p;

@@ -110,6 +110,18 @@ def test_both_hoods_equal_x_runs_and_duplicates():
     assert_both_equal(pts, off, out, cnt)
 
 
+@pytest.mark.parametrize("strip", [8, 16, 32])
+def test_upper_hood_of_convex_arms(strip):
+    # a U-shaped set: the upper hood is a few corners, and most tiles lie on
+    # a falling or rising convex arm (the tile kernel's chord test)
+    u = synth.parabola(200000, 20, 1, seed=50)
+    u[:, 1] = -u[:, 1]
+    fall = u[:100000].copy()
+    pts, off = synth.concat_sets([u, fall, u[100000:].copy()])
+    out, cnt = both_hoods(pts, off, strip=strip)
+    assert_both_equal(pts, off, out, cnt)
+
+
 def test_upper_half_matches_the_upper_only_plan():
     pts, off = _mixed_sets(7)
     out, cnt = both_hoods(pts, off)
