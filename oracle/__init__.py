@@ -13,7 +13,9 @@ Contents:
   * ``brute``      -- O(n^3) evaluation of the hood's definition (tiny n);
   * ``invariants`` -- exact checks that characterise the strict upper hood;
   * ``bridge``     -- the per-merge quantities of the paper's match-and-merge
-    step (tangent classifiers g and f, the common tangent) by brute force.
+    step (tangent classifiers g and f, the common tangent) by brute force;
+  * ``unsorted_hull`` -- any of the three for points in any order: a stable
+    sort by x in front (a library sort as one step).
 """
 from __future__ import annotations
 
@@ -162,3 +164,24 @@ def orient_signs(a, b, c) -> np.ndarray:
     if rc != OK:
         raise ValueError(f"oracle: invalid coordinate (status {rc})")
     return out[:m].copy()
+
+def sort_order(xy) -> np.ndarray:
+    """The order in which the hull of points given in any order is taken:
+    stable by x (equal x keep their input order, so every tie rule that
+    prefers the lowest index still prefers the lowest input index).  -0.0
+    and +0.0 compare equal."""
+    a = _pts(xy)
+    return np.argsort(a[:, 0], kind="stable").astype(np.int64)
+
+
+def unsorted_hull(xy, hood: str = "upper"):
+    """(status, indices) of the upper hood, lower hood or convex hull of
+    points in any order: the hull of the points sorted by ``sort_order``,
+    its corners mapped back to input indices (corners left to right; the
+    convex hull counter-clockwise)."""
+    a = _pts(xy)
+    order = sort_order(a)
+    fn = {"upper": upper_hull_status, "lower": lower_hull_status,
+          "convex": convex_hull_status}[hood]
+    rc, idx = fn(a[order])
+    return rc, order[idx].astype(np.int32)

@@ -157,3 +157,67 @@ def test_error_codes_match_the_upper_hood():
     for bad in ([[0.5, 0.0], [0.25, 0.0]], [[0.5, 2.0 ** -40]], [[1.5, 0.0]]):
         assert oracle.lower_hull_status(bad)[0] == oracle.upper_hull_status(bad)[0] < 0
         assert oracle.convex_hull_status(bad)[0] == oracle.upper_hull_status(bad)[0]
+
+
+# -------------------------------------------------------------- unsorted input
+def _brute_by_x(xy, corners):
+    X, _ = brute.exact_ints(xy)
+    return sorted(corners, key=lambda i: X[i])
+
+
+def test_unsorted_matches_brute_force_on_shuffled_lattices():
+    rng = np.random.default_rng(7)
+    for seed in range(300):
+        xy = synth.lattice_points(1 + seed % 12, (4, 8, 16)[seed % 3], seed=900 + seed)
+        sh = xy[rng.permutation(len(xy))]
+        rc, up = oracle.unsorted_hull(sh, "upper")
+        assert rc == 0 and list(up) == _brute_unsorted(sh)
+        # the upper hood's brute force does not depend on the input order either
+        assert list(up) == _brute_by_x(sh, brute.upper_hull_brute(sh))
+        rc, lo = oracle.unsorted_hull(sh, "lower")
+        assert rc == 0 and list(lo) == _brute_unsorted(sh, lower=True)
+        if seed % 3 == 0:
+            rc, full = oracle.unsorted_hull(sh, "convex")
+            assert rc == 0 and sorted(full) == _brute_hull_corners_unsorted(sh)
+            assert invariants.check_convex_hull(sh, full) == []
+
+
+def _brute_unsorted(xy, lower=False):
+    """The hood's definition evaluated on points in any order: i is a corner
+    iff no point at its x is higher (lower hood: lower), or equally high
+    with a lower index, and no pair a, b with X_a < X_i < X_b has i on or
+    below (lower hood: on or above) segment ab.  Corners by x."""
+    X, Y = brute.exact_ints(xy)
+    n = len(X)
+    sgn = -1 if lower else 1
+    out = []
+    for i in range(n):
+        if any(j != i and X[j] == X[i] and (sgn * Y[j] > sgn * Y[i] or (Y[j] == Y[i] and j < i))
+               for j in range(n)):
+            continue
+        if any(sgn * brute.det(X, Y, a, b, i) <= 0 for a in range(n) for b in range(n)
+               if X[a] < X[i] < X[b]):
+            continue
+        out.append(i)
+    return sorted(out, key=lambda i: X[i])
+
+
+def _brute_hull_corners_unsorted(xy):
+    # the corner set does not depend on the order; ties to the lowest index
+    return brute.convex_hull_corners_brute(xy)
+
+
+def test_unsorted_sorted_input_is_unchanged():
+    xy = synth.uniform(5000, 20, seed=8)
+    for hood, fn in (("upper", oracle.upper_hull), ("lower", oracle.lower_hull),
+                     ("convex", oracle.convex_hull)):
+        rc, got = oracle.unsorted_hull(xy, hood)
+        assert rc == 0 and np.array_equal(got, fn(xy))
+
+
+def test_unsorted_tie_rules_follow_input_index():
+    # identical points in reverse input order: the lowest input index wins
+    xy = np.array([[0.75, 0.5], [0.25, 0.25], [0.75, 0.5], [0.25, 0.25], [0.5, -0.5]], np.float32)
+    assert list(oracle.unsorted_hull(xy, "upper")[1]) == [1, 0]
+    assert list(oracle.unsorted_hull(xy, "lower")[1]) == [1, 4, 0]
+    assert list(oracle.unsorted_hull(xy, "convex")[1]) == [1, 4, 0]
