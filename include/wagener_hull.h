@@ -89,6 +89,14 @@ typedef struct {
 #define UH_FLAG_BOTH_HOODS 8u     /* also the lower hood of every set, from */
                                   /* the same single read of the points     */
                                   /* (output layout at upper_hull_plan_run) */
+#define UH_FLAG_UNSORTED 16u      /* points of a set in any order: the plan */
+                                  /* sorts every set by x on the device     */
+                                  /* first (stable: equal x keep input      */
+                                  /* order, so tie rules refer to input     */
+                                  /* indices); corners are reported as      */
+                                  /* input indices, left to right.  At most */
+                                  /* 2^32 - 1 points; adds about 36 bytes   */
+                                  /* per point of workspace.                */
 
 /* ------------------------------------------------------------ single set */
 /*
@@ -173,6 +181,16 @@ int upper_hull_plan_run(upper_hull_plan *plan, const float *points,
 
 /* Free a plan and its device memory (synchronises its device first). */
 void upper_hull_plan_destroy(upper_hull_plan *plan);
+
+/*
+ * For a plan built with UH_FLAG_UNSORTED: the plan's own device buffers that
+ * hold, after a run (once its stream has reached that point), every set's
+ * points sorted by x (*sorted_points, float32 pairs, set s at
+ * set_offsets[s]) and their set-relative input indices (*perm).  Owned by the
+ * plan; overwritten by its next run.  UH_ERR_ARG for other plans.
+ */
+int upper_hull_plan_sorted(const upper_hull_plan *plan, const float **sorted_points,
+                           const int32_t **perm);
 
 /* Number of kernel launches one run of the plan enqueues (for profiling). */
 int upper_hull_plan_launches(const upper_hull_plan *plan);

@@ -34,11 +34,13 @@ UH_FLAG_FORCE_FALLBACK = 1
 UH_FLAG_NO_VALIDATE = 2
 UH_FLAG_GRAPH = 4
 UH_FLAG_BOTH_HOODS = 8
+UH_FLAG_UNSORTED = 16
 
 EXPORTS = (
     "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
-    "upper_hull_plan_set_probe", "upper_hull_autotune", "upper_hull_read_reference",
+    "upper_hull_plan_set_probe", "upper_hull_plan_sorted", "upper_hull_autotune",
+    "upper_hull_read_reference",
     "upper_hull_bridge", "upper_hull_orient",
 )
 
@@ -84,6 +86,8 @@ def load_library():
     lib.upper_hull_plan_set_probe.restype = ctypes.c_int
     lib.upper_hull_autotune.argtypes = [p, p, i32, ctypes.c_uint32, i32, p, p, p]
     lib.upper_hull_autotune.restype = ctypes.c_int
+    lib.upper_hull_plan_sorted.argtypes = [p, ctypes.POINTER(p), ctypes.POINTER(p)]
+    lib.upper_hull_plan_sorted.restype = ctypes.c_int
     lib.upper_hull_read_reference.argtypes = [p, i64, i32, p, p]
     lib.upper_hull_read_reference.restype = ctypes.c_int
     lib.upper_hull_bridge.argtypes = [p, i32, p, i32, i32, p, p]
@@ -188,6 +192,23 @@ class Plan:
         """Record raw hipEvent_t handles (ints) around the tile kernel."""
         _check(load_library().upper_hull_plan_set_probe(
             self._h, ctypes.c_void_p(before), ctypes.c_void_p(after)))
+
+    def sorted_view(self):
+        """(sorted points, permutation) of the last run of an UH_FLAG_UNSORTED
+        plan, copied to the host as numpy arrays (synchronises the device)."""
+        torch = _torch()
+        sp, pm = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(load_library().upper_hull_plan_sorted(self._h, ctypes.byref(sp), ctypes.byref(pm)))
+        torch.cuda.synchronize()
+        n = self.total
+        xy = np.empty((n, 2), np.float32)
+        perm = np.empty(n, np.int32)
+        if n:
+            hip = ctypes.CDLL("libamdhip64.so")
+            d2h = 2  # hipMemcpyDeviceToHost
+            assert hip.hipMemcpy(ctypes.c_void_p(xy.ctypes.data), sp, ctypes.c_size_t(8 * n), d2h) == 0
+            assert hip.hipMemcpy(ctypes.c_void_p(perm.ctypes.data), pm, ctypes.c_size_t(4 * n), d2h) == 0
+        return xy, perm
 
     def run(self, points, out_idx, out_counts, stats=None, stream=None):
         torch = _torch()

@@ -12,8 +12,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "wagener_hull.hip")
-SOURCES = [SRC, os.path.join(HERE, "csrc", "read_reference.hip")]
+SOURCES = [SRC, os.path.join(HERE, "csrc", "read_reference.hip"),
+           os.path.join(HERE, "csrc", "radix_sort.hip")]
 DEPS = [*SOURCES, os.path.join(HERE, "csrc", "uh_device.hpp"),
+        os.path.join(HERE, "csrc", "radix_sort.hpp"),
         os.path.join(ROOT, "include", "wagener_hull.h")]
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libwagener_hull.so")

@@ -41,6 +41,7 @@
 #include <tuple>
 #include <vector>
 
+#include "radix_sort.hpp"
 #include "uh_device.hpp"
 #include "wagener_hull.h"
 
@@ -1174,6 +1175,23 @@ __global__ void hull_assemble_kernel(const int32_t *hood, const int32_t *cnt, in
   if (t == 0) *out_count = (int32_t)total;
 }
 
+// --------------------------------------------------------- unsorted input
+// Maps the corners of every (virtual) set from sorted positions back to
+// set-relative input indices: out[k] = perm[set start + out[k]].  One
+// workgroup per set; the set of a lower hood is set - in_sets.
+__global__ void unsort_kernel(const int64_t *set_start, int32_t in_sets, const int32_t *perm,
+                              int32_t *out_idx, const int32_t *out_counts) {
+  const int v = blockIdx.x;
+  const int32_t c = out_counts[v];
+  const int64_t src = set_start[v < in_sets ? v : v - in_sets];
+  const int64_t n = set_start[(v < in_sets ? v : v - in_sets) + 1] - src;
+  int32_t *o = out_idx + set_start[v];
+  for (int k = threadIdx.x; k < c; k += blockDim.x) {
+    const int32_t q = o[k];
+    if (q >= 0 && q < n) o[k] = perm[src + q];  // always, for a hood of the set
+  }
+}
+
 // ---------------------------------------------------------------- probes
 __global__ void bridge_kernel(const float2 *P, int hp, const float2 *Q, int hq,
                               int L, int32_t *out_ab) {
@@ -1231,6 +1249,10 @@ struct upper_hull_plan {
   hipStream_t cap_stream = nullptr;
   hipEvent_t probe_before = nullptr, probe_after = nullptr;
   int32_t *hull_idx = nullptr, *hull_cnt = nullptr;  // convex_hull: both hoods before joining
+  bool unsorted = false;            // sort every set by x first (UH_FLAG_UNSORTED)
+  uh_rs::RadixPlan rs;
+  float2 *sorted = nullptr;         // [in_N] the points in sorted order
+  int32_t *perm = nullptr;          // [in_N] their set-relative input indices
   std::mutex mu;
 };
 
@@ -1267,11 +1289,20 @@ void free_plan_memory(upper_hull_plan *p) {
   hipFree(p->group_max);
   hipFree(p->hull_idx);
   hipFree(p->hull_cnt);
+  uh_rs::radix_plan_free(&p->rs);
+  hipFree(p->sorted);
+  hipFree(p->perm);
   for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
   if (p->cap_stream) hipStreamDestroy(p->cap_stream);
 }
 
-int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
+int enqueue_run(upper_hull_plan *p, const RunArgs &A0, hipStream_t stream) {
+  RunArgs A = A0;
+  if (p->unsorted) {  // the sort by x in front: the hull reads the sorted copy
+    const int rc = uh_rs::radix_sort_enqueue(p->rs, A0.pts, p->in_N, p->sorted, p->perm, stream);
+    if (rc) return rc;
+    A.pts = p->sorted;
+  }
   // Per-set status starts at zero (plan creation) and the final merge of a
   // set that saw an error zeroes it again, so the clearing pass is needed
   // only for stats counters and for empty sets' counts.
@@ -1310,6 +1341,9 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A, hipStream_t stream) {
       hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), dim3(p->pass_items[ps]), dim3(BLOCK), 0,
                          stream, A, p->d_items[ps], ccnt, p->d_cnt[ps]);
   }
+  if (p->unsorted)
+    hipLaunchKernelGGL(unsort_kernel, dim3(p->S), dim3(256), 0, stream, p->d_set_start, p->in_S,
+                       p->perm, A.out_idx, A.out_counts);
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
 
@@ -1387,6 +1421,8 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   }
   if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
   if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
+  // the sort's positions are 32-bit
+  if ((flags & UH_FLAG_UNSORTED) && set_offsets[num_sets] > (int64_t)UINT32_MAX) return UH_ERR_ARG;
 
   // With both hoods the schedule covers 2 * num_sets sets over 2 * N slots:
   // set num_sets + s is the lower hood of set s (the mirrored points), its
@@ -1532,6 +1568,12 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     for (const MergeItem &m : items) wide = wide || m.nch > BLOCK;
     p->pass_wide.push_back(wide);
   }
+  if (!rc && (flags & UH_FLAG_UNSORTED)) {
+    p->unsorted = true;
+    rc = uh_rs::radix_plan_build(set_offsets, num_sets, &p->rs);
+    rc = rc ? rc : dalloc(&p->sorted, (size_t)p->in_N);
+    rc = rc ? rc : dalloc(&p->perm, (size_t)p->in_N);
+  }
   rc = rc ? rc : dalloc(&p->ws_xy, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws_idx, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws2_xy, (size_t)p->N);
@@ -1554,9 +1596,19 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   return UH_OK;
 }
 
+int upper_hull_plan_sorted(const upper_hull_plan *plan, const float **sorted_points,
+                           const int32_t **perm) {
+  if (!plan || !plan->unsorted || !sorted_points || !perm) return UH_ERR_ARG;
+  *sorted_points = (const float *)plan->sorted;
+  *perm = plan->perm;
+  return UH_OK;
+}
+
 int upper_hull_plan_launches(const upper_hull_plan *plan) {
   if (!plan) return UH_ERR_ARG;
-  return (int)plan->has_empty + (plan->ntiles > 0) + (int)plan->pass_items.size();
+  const int sort = plan->unsorted && plan->rs.nblocks > 0 ? 5 * uh_rs::RS_PASSES : 0;
+  return sort + (int)plan->has_empty + (plan->ntiles > 0) + (int)plan->pass_items.size() +
+         (plan->unsorted ? 1 : 0);
 }
 
 int upper_hull_plan_set_probe(upper_hull_plan *plan, hipEvent_t before,
