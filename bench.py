@@ -84,20 +84,34 @@ class HipEvents:
         self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def cpu_baseline(pts_np, off, budget_s: float, both: bool = False):
+def cpu_baseline(pts_np, off, budget_s: float, both: bool = False, unsorted: bool = False):
     """The oracle over the whole workload, repeated until budget_s; with both,
     the upper and the lower hood of every set (outputs laid out as the
-    library's two halves)."""
+    library's two halves); with unsorted, a stable sort of every set by x in
+    front and the corners mapped back to input indices."""
     import numpy as np
     import oracle
     t_total, reps = 0.0, 0
     out = cnt = None
+    N = len(pts_np)
     while reps < 1 or t_total < budget_s:
         t0 = time.perf_counter()
-        out, cnt = oracle.upper_hull_batched(pts_np, off)
+        src, perm = pts_np, None
+        if unsorted:
+            perm = np.concatenate([off[s] + oracle.sort_order(pts_np[off[s]:off[s + 1]])
+                                   for s in range(len(off) - 1)] or [np.zeros(0, np.int64)])
+            src = pts_np[perm]
+        out, cnt = oracle.upper_hull_batched(src, off)
         if both:
-            lo, lcnt = oracle.lower_hull_batched(pts_np, off)
-            out, cnt = np.concatenate([out[:len(pts_np)], lo]), np.concatenate([cnt, lcnt])
+            lo, lcnt = oracle.lower_hull_batched(src, off)
+            out, cnt = np.concatenate([out[:N], lo]), np.concatenate([cnt, lcnt])
+        if unsorted:  # sorted positions -> set-relative input indices
+            H = 2 if both else 1
+            for h in range(H):
+                for s in range(len(off) - 1):
+                    a = h * N + off[s]
+                    c = int(cnt[h * (len(off) - 1) + s])
+                    out[a:a + c] = perm[off[s] + out[a:a + c]] - off[s]
         t_total += time.perf_counter() - t0
         reps += 1
     return len(pts_np) * reps / t_total, reps, t_total, out, cnt
@@ -126,6 +140,9 @@ def main():
     ap.add_argument("--both-hoods", action="store_true",
                     help="upper and lower hood of every set from the same read (the convex "
                          "hull's two halves)")
+    ap.add_argument("--unsorted", action="store_true",
+                    help="shuffle every set (seeded) and let the library sort it by x on the "
+                         "device first")
     ap.add_argument("--flush", action="store_true",
                     help="cold caches: overwrite a 1 GiB buffer before every timed step (outside "
                          "the step's own events), so the input is read from HBM, not the 256 MB "
@@ -154,6 +171,14 @@ def main():
     log(f"[bench] generated {args.workload}: {len(pts_np)} points, {len(off) - 1} sets "
         f"in {time.perf_counter() - t0:.1f}s")
 
+    if args.unsorted:
+        t0 = time.perf_counter()
+        rng = np.random.default_rng(20350)
+        for s in range(len(off) - 1):
+            seg = pts_np[off[s]:off[s + 1]]
+            seg[...] = seg[rng.permutation(len(seg))]
+        log(f"[bench] shuffled every set in {time.perf_counter() - t0:.1f}s")
+
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -167,7 +192,8 @@ def main():
     N, S = len(pts_np), len(off) - 1
     flags = (uh.UH_FLAG_GRAPH if args.graph else 0) | \
         (uh.UH_FLAG_FORCE_FALLBACK if args.force_fallback else 0) | \
-        (uh.UH_FLAG_BOTH_HOODS if args.both_hoods else 0)
+        (uh.UH_FLAG_BOTH_HOODS if args.both_hoods else 0) | \
+        (uh.UH_FLAG_UNSORTED if args.unsorted else 0)
     H = 2 if args.both_hoods else 1  # hoods per set
     fan_in = 0
     tuned = None
@@ -246,7 +272,7 @@ def main():
     plain = None
     if args.compare_plain:
         log(f"[bench] plain per-set method: {S} plans ...")
-        pflags = flags & uh.UH_FLAG_BOTH_HOODS
+        pflags = flags & (uh.UH_FLAG_BOTH_HOODS | uh.UH_FLAG_UNSORTED)
         plans = [uh.upper_hull_plan_create([0, int(off[s + 1] - off[s])], strip=args.strip,
                                            flags=pflags) for s in range(S)]
         scratch_idx = torch.empty(max(H * int(np.max(np.diff(off))), 1), dtype=torch.int32,
@@ -296,7 +322,8 @@ def main():
     roofline = None
     if tile_ms:
         achieved = alg_tile / (tile_ms * 1e-3) / 1e9
-        traffic = None if args.both_hoods else load_traffic(args.workload, args.strip)
+        traffic = None if (args.both_hoods or args.unsorted) else \
+            load_traffic(args.workload, args.strip)
         roofline = {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -309,10 +336,12 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
         rate, reps, secs, ref_out, ref_cnt = cpu_baseline(pts_np, off, args.cpu_budget,
-                                                          both=args.both_hoods)
+                                                          both=args.both_hoods,
+                                                          unsorted=args.unsorted)
         cpu = {"value": round(rate, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
                "sample": f"whole workload ({N} points, {S} sets"
-                         f"{', both hoods' if H == 2 else ''}), {reps} run(s), "
+                         f"{', both hoods' if H == 2 else ''}"
+                         f"{', sorted by x first' if args.unsorted else ''}), {reps} run(s), "
                          f"{secs:.1f} s, single thread"}
         got = out_idx.cpu().numpy()
         voff = np.concatenate([off[:-1] + h * N for h in range(H)])  # start of every output set
@@ -331,6 +360,7 @@ def main():
                    "graph": bool(args.graph), "force_fallback": bool(args.force_fallback),
                    "cold_cache": bool(args.flush),
                    "hoods": "upper and lower" if H == 2 else "upper",
+                   "input_order": "shuffled (sorted on the device)" if args.unsorted else "by x",
                    "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),
                    "fallback_rate": (fallbacks / evals) if evals else 0.0,

@@ -7,13 +7,20 @@
 // in input order, so every "lowest index" tie rule still refers to input
 // indices; the hull indices are mapped back through the permutation.
 //
-// Least-significant-digit radix sort, four passes of 8 bits over the float
-// bits of x with the sign bit cleared (for x in [0, 1] the bits order like
-// the values; -0.0 sorts with +0.0).  Sets are sorted independently in one
-// pass sequence: every block of up to RS_TILE points lies in one set, and the
-// per-block digit counts are laid out set by set, digit-major within a set,
-// so one exclusive scan over all of them gives every (set, digit, block) its
-// absolute output position.
+// Least-significant-digit radix sort, five passes of 6 bits over the low 30
+// float bits of x (for x in [0, 1] those order like the values, and -0.0
+// sorts with +0.0; a value outside [0, 1] lands somewhere and is reported by
+// the hull's checks).  Sets are sorted independently in one pass sequence:
+// every block of up to RS_TILE points lies in one set, and a key's output
+// position is its set's start, plus the keys of its set with a smaller
+// digit, plus those with its digit in earlier blocks of the set, plus its
+// rank in its block.  The per-block digit counts are summed over chunks of
+// blocks, scanned over the chunks of each set, and rescanned inside each
+// chunk, all with one lane per digit and coalesced rows.  Six-bit digits
+// give runs of about 64 keys per digit and block; between passes a key
+// travels with its payload as one 12-byte record, so the scattered stores of
+// a pass write runs of about 768 bytes (separate key and payload arrays,
+// which would let the count pass read 4 bytes a key, measured slower).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,27 +31,43 @@ namespace uh_rs {
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;                      // keys per thread
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;    // keys per block
-constexpr int RS_BINS = 256;
-constexpr int RS_PASSES = 4;
+constexpr int RS_BITS = 6;
+constexpr int RS_BINS = 1 << RS_BITS;
+constexpr int RS_PASSES = 5;
+constexpr int RS_CHUNK = 256;  // blocks per chunk of the scan
 
 struct RadixItem {   // one block of the sort: a range of one set
   int64_t start;     // first point (absolute)
   int32_t len;       // 1 .. RS_TILE
   int32_t rel0;      // start minus the set's start
-  int32_t hist0;     // counts of digit d go to hist[hist0 + d * nb]
-  int32_t nb;        // blocks of this set
+};
+
+struct RadixChunk {  // up to RS_CHUNK consecutive blocks of one set
+  int32_t b0, nb;    // first block, blocks
+  int32_t set;       // index among the non-empty sets
+  int32_t pad;
+};
+
+struct RadixSet {    // a non-empty set
+  int64_t start;     // its first point
+  int32_t c0, nc;    // its chunks
+};
+
+struct RadixRec {    // a key and its payload between passes (12 bytes)
+  uint32_t key;      // bits of x
+  float y;
+  int32_t idx;       // set-relative input index
 };
 
 struct RadixPlan {
-  int32_t nblocks = 0;
-  int64_t nhist = 0;             // RS_BINS * nblocks
-  int32_t npart = 0;             // scan partials
+  int32_t nblocks = 0, nchunks = 0, nsets = 0;
   RadixItem *items = nullptr;    // [nblocks]
-  uint32_t *hist = nullptr;      // [nhist]
-  uint32_t *part = nullptr;      // [npart]
-  uint32_t *key[2] = {nullptr, nullptr};  // x bits, per pass (ping-pong)
-  float *y[2] = {nullptr, nullptr};
-  int32_t *idx[2] = {nullptr, nullptr};   // set-relative input index
+  RadixChunk *chunks = nullptr;  // [nchunks]
+  RadixSet *sets = nullptr;      // [nsets]
+  uint32_t *hist = nullptr;      // [nblocks * RS_BINS] digit counts, then output starts
+  uint32_t *csum = nullptr;      // [nchunks * RS_BINS] chunk sums, then chunk starts
+  uint32_t *dbase = nullptr;     // [nsets * RS_BINS] where each digit of a set starts
+  RadixRec *rec[2] = {nullptr, nullptr};  // records between passes (ping-pong)
 };
 
 // Builds the blocks and allocates the buffers for sets set_offsets[0..S].
