@@ -108,7 +108,7 @@ typedef struct {
  *   out_count device int32[1]: the corner count, or a negative data-error
  *             status.
  *   stream    HIP stream the work is enqueued on.
- * The library keeps a plan (schedule + workspace of about 24 bytes per
+ * The library keeps a plan (schedule + workspace of about 12 bytes per
  * point) per distinct n, built on first use; building one is not allowed
  * while `stream` is capturing (UH_ERR_CAPTURE): call once before capture.
  * This is the paper's whole program (its stage loop and match_and_merge
@@ -130,7 +130,7 @@ int upper_hull(const float *points, int64_t n, int32_t *out_idx,
  *   out_idx    device int32[n]: every index appears at most once.
  *   out_count  device int32[1]: the corner count, or a negative data-error
  *              status (the same checks as upper_hull).
- * Keeps its own cached plan per n (workspace about 48 bytes per point plus
+ * Keeps its own cached plan per n (workspace about 24 bytes per point plus
  * 8 bytes per point of hood buffers); the same rules as upper_hull apply
  * (no plan building during capture, no overlapping calls for one n).
  */
@@ -149,7 +149,7 @@ typedef struct upper_hull_plan upper_hull_plan;
  *   config       NULL for defaults.
  *   out_plan     receives the plan (owned by the caller; destroy it with
  *                upper_hull_plan_destroy).
- * Allocates the schedule tables and the workspace (about 24 bytes per point,
+ * Allocates the schedule tables and the workspace (about 12 bytes per point,
  * twice that with UH_FLAG_BOTH_HOODS,
  * plus a few bytes per tile) on the current device.
  */

@@ -88,8 +88,6 @@ struct RunArgs {
   const int64_t *set_start;  // [S + 1]
   float2 *ws_xy;             // [N] corner coordinates at their slots
   int32_t *ws_idx;           // [N] set-relative index of each corner
-  float2 *ws2_xy;            // [N] second workspace: the global merge path
-  int32_t *ws2_idx;          //     alternates between the two
   int32_t *set_status;       // [S] worst data error seen (0 = none)
   int32_t *out_idx;
   int32_t *out_counts;
@@ -800,13 +798,34 @@ __device__ __forceinline__ void block_excl_max(float v, float all_pre, float all
   __syncthreads();  // sw may be reused
 }
 
+// A block of the merge kernel's global path: children k0 .. k1 - 1, child k
+// keeping corners [lo[k], lo[k] + cum[k + 1] - cum[k]) of its slot; element
+// e of the block is element c0 + e of the item (cum: exclusive prefix of the
+// kept counts over the item's children, in LDS).
+struct Rope {
+  const float2 *xy;
+  const int *cum, *lo;
+  int64_t off, stride;
+  int k0, k1, c0;
+  // workspace position of the item's element gi (cum[k0] <= gi < cum[k1])
+  __device__ __forceinline__ int64_t where(int gi) const {
+    int l = k0, h = k1;
+    while (h - l > 1) {
+      const int mid = (l + h) >> 1;
+      if (cum[mid] <= gi) l = mid;
+      else h = mid;
+    }
+    return off + (int64_t)l * stride + lo[l] + (gi - cum[l]);
+  }
+  __device__ __forceinline__ float2 operator[](int e) const { return xy[where(c0 + e)]; }
+};
+
 // One workgroup of BLK threads merges the hoods of up to BLK consecutive
 // blocks of the previous level of one set (log2 BLK more rounds).  When their corners fit
 // in LDS: gather them back to back, six rounds inside each wave (64
 // children -> 1), then wave 0 merges the four wave hoods.  Otherwise the
-// same rounds run in place in the workspace (global memory), each merge by
-// a group of lanes with workgroup barriers between the reads and writes of
-// the compaction.
+// same rounds run over the workspace (global memory), each merge by a group
+// of lanes, narrowing per-child intervals instead of moving corners.
 template <int BLK, int VMX>
 __global__ __launch_bounds__(BLK) void merge_kernel(
     RunArgs A, const MergeItem *items, const int32_t *child_cnt, int32_t *cnt_out) {
@@ -1038,78 +1057,92 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     return;
   }
 
-  // ---- too large for LDS: the same rounds in the workspace, each round
-  // copying the merged hoods into the other workspace (no copy overlaps its
-  // source, so every thread copies its share with many loads in flight)
+  // ---- too large for LDS: the same rounds over the workspace, moving no
+  // corner.  A merge keeps a prefix of P and a suffix of Q, so every block
+  // is a run of children, each keeping one interval [klo, klo + bcnt) of its
+  // corners; a round only narrows intervals, the searches read the corners
+  // where they are (Rope), and the result is gathered once at the end.
   if (pts && c > 0)  // point-list children first become hoods, in place
     bcnt[tid] = chain_inplace(A.ws_xy + g, A.ws_idx + g, c, oc, fe);
-  __syncthreads();
-  int flip = 0;  // 0: the blocks are in ws, 1: in ws2
+  int *cum = bid;            // [BLK + 1] exclusive prefix of the kept counts
+  int *klo = bid + BLK + 1;  // [BLK] start of each child's kept interval
+  klo[tid] = 0;
+  auto rescan = [&]() {
+    __syncthreads();
+    int tot;
+    cum[tid] = block_exclusive_scan<BLK>(tid < nch ? bcnt[tid] : 0, swave, tot);
+    if (tid == 0) cum[BLK] = tot;
+    __syncthreads();
+  };
+  rescan();
 #pragma unroll 1
   for (int j = 0; (1 << j) < nch; ++j) {
     const int M = npow >> (j + 1);
     const int G = BLK / M;
     const int m = tid / G, t = tid % G;
     const int lp = (2 * m) << j, lq = (2 * m + 1) << j;
-    const float2 *Sxy = flip ? A.ws2_xy : A.ws_xy;
-    const int32_t *Sid = flip ? A.ws2_idx : A.ws_idx;
-    float2 *Dxy = flip ? A.ws_xy : A.ws2_xy;
-    int32_t *Did = flip ? A.ws_idx : A.ws2_idx;
-    const bool has_p = lp < nch, active = lp < nch && lq < nch;
-    const int64_t op = it.off + lp * it.stride, oq = it.off + lq * it.stride;
-    int a = -1, b = 0, hp = has_p ? bcnt[lp] : 0, hqe = 0, qs = 0;
+    const int le = min((2 * m + 2) << j, nch);
+    const bool active = lq < nch;
+    int a = -1, b = 0;
     if (active) {
-      const float2 *P = Sxy + op, *Q = Sxy + oq;
-      const int hq = bcnt[lq];
+      Rope P{A.ws_xy, cum, klo, it.off, it.stride, lp, lq, cum[lp]};
+      Rope Q{A.ws_xy, cum, klo, it.off, it.stride, lq, le, cum[lq]};
+      int hp = cum[lq] - cum[lp], qs = 0;
+      const int hq = cum[le] - cum[lq];
       if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
-      hqe = hq - qs;
+      const int hqe = hq - qs;
       a = hp - 1;
+      Q.c0 += qs;
       const int L = G < 64 ? G : 64;
       if (hp > 0 && hqe > 0 && t < L)
-        bridge_search<const float2 *>(P, hp, Q + qs, hqe, L, t, (tid & 63) - t, a, b, oc,
-                                      fe);
+        bridge_search<Rope>(P, hp, Q, hqe, L, t, (tid & 63) - t, a, b, oc, fe);
+      b += qs;  // Q's first kept corner
     }
-    __syncthreads();  // searches done
-    if (G > 64) {
-      if (t == 0) sres[m] = make_int2(a, b);
-      __syncthreads();
-      const int2 rr = sres[m];
-      a = rr.x;
-      b = rr.y;
+    __syncthreads();  // searches done; every merge's result to sres
+    if (t == 0) sres[m] = active ? make_int2(a + 1, b) : make_int2(INT32_MAX, 0);
+    __syncthreads();
+    if (tid < nch) {  // child tid narrows its interval
+      const int mk = tid >> (j + 1);
+      const int2 r = sres[mk];
+      const int lpk = (2 * mk) << j, lqk = (2 * mk + 1) << j;
+      const int cnt = bcnt[tid];
+      if (tid < lqk) {  // in P: keeps P's corners below r.x
+        bcnt[tid] = min(max(r.x - (cum[tid] - cum[lpk]), 0), cnt);
+      } else {  // in Q: drops Q's corners below r.y
+        const int drop = min(max(r.y - (cum[tid] - cum[lqk]), 0), cnt);
+        klo[tid] += drop;
+        bcnt[tid] = cnt - drop;
+      }
     }
-    // P[0..a] ++ Q[qs + b ..] to the other workspace at P's slot; a block
-    // without a partner this round is copied whole
-    const int np = active ? a + 1 : hp;
-    const int nq = active ? hqe - b : 0;
-    const int64_t qsrc = oq + qs + b - np;  // source of merged entry e >= np
-    for (int e0 = 0; e0 < np + nq; e0 += 8 * G) {
-      float2 vx[8];
+    rescan();
+  }
+  // the result: corner e lives in child l with cum[l] <= e < cum[l + 1]
+  const int hc = cum[BLK];
+  const Rope R{A.ws_xy, cum, klo, it.off, it.stride, 0, nch, 0};
+  if (it.final_) {
+    int32_t *dst = A.out_idx + A.set_start[it.set];
+    for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {
       int32_t vi[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * G + t;
-        if (e < np + nq) {
-          const int64_t src = e < np ? op + e : qsrc + e;
-          vx[u] = Sxy[src];
-          vi[u] = Sid[src];
-        }
+        const int e = e0 + u * BLK + tid;
+        if (e < hc) vi[u] = A.ws_idx[R.where(e)];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * G + t;
-        if (e < np + nq) {
-          Dxy[op + e] = vx[u];
-          Did[op + e] = vi[u];
-        }
+        const int e = e0 + u * BLK + tid;
+        if (e < hc) dst[e] = vi[u];
       }
     }
-    __syncthreads();  // every lane has read bcnt
-    if (t == 0 && has_p) bcnt[lp] = np + nq;
-    flip ^= 1;
-    __syncthreads();
-  }
-  if (flip && !it.final_) {  // the result back to ws, where the next level reads it
-    const int hc = bcnt[0];
+    if (tid == 0) {
+      const int st = A.set_status[it.set];
+      A.out_counts[it.set] = st ? st : hc;
+      if (st) A.set_status[it.set] = 0;  // zero again for the next run
+    }
+  } else {
+    // compact to the item's slot: corner e comes from at or after slot
+    // position e (a child keeps at most its slot's length), so a chunk read
+    // whole before it is written never overwrites a corner still to be read
     for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {
       float2 vx[8];
       int32_t vi[8];
@@ -1117,10 +1150,12 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * BLK + tid;
         if (e < hc) {
-          vx[u] = A.ws2_xy[it.off + e];
-          vi[u] = A.ws2_idx[it.off + e];
+          const int64_t src = R.where(e);
+          vx[u] = A.ws_xy[src];
+          vi[u] = A.ws_idx[src];
         }
       }
+      __syncthreads();
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * BLK + tid;
@@ -1129,19 +1164,8 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
           A.ws_idx[it.off + e] = vi[u];
         }
       }
+      __syncthreads();
     }
-  }
-  const int hc = bcnt[0];
-  const int32_t *res_id = (flip ? A.ws2_idx : A.ws_idx) + it.off;
-  if (it.final_) {
-    int32_t *dst = A.out_idx + A.set_start[it.set];
-    for (int k = tid; k < hc; k += BLK) dst[k] = res_id[k];
-    if (tid == 0) {
-      const int st = A.set_status[it.set];
-      A.out_counts[it.set] = st ? st : hc;
-      if (st) A.set_status[it.set] = 0;  // zero again for the next run
-    }
-  } else {
     if (tid == 0) cnt_out[blockIdx.x] = hc;
   }
   if (it.final_)  // the set's group maxima, zero again for the next run
@@ -1241,8 +1265,8 @@ struct upper_hull_plan {
   int32_t *d_cnt0 = nullptr;
   std::vector<MergeItem *> d_items;
   std::vector<int32_t *> d_cnt;   // per pass: item corner counts
-  float2 *ws_xy = nullptr, *ws2_xy = nullptr;
-  int32_t *ws_idx = nullptr, *ws2_idx = nullptr;
+  float2 *ws_xy = nullptr;
+  int32_t *ws_idx = nullptr;
   int32_t *set_status = nullptr;
   // graph cache: (points, out_idx, out_counts, stats) -> exec
   std::map<std::tuple<const void *, void *, void *, void *>, hipGraphExec_t> graphs;
@@ -1282,8 +1306,6 @@ void free_plan_memory(upper_hull_plan *p) {
   for (auto *q : p->d_cnt) hipFree(q);
   hipFree(p->ws_xy);
   hipFree(p->ws_idx);
-  hipFree(p->ws2_xy);
-  hipFree(p->ws2_idx);
   hipFree(p->set_status);
   hipFree(p->tile_max);
   hipFree(p->group_max);
@@ -1576,8 +1598,6 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   }
   rc = rc ? rc : dalloc(&p->ws_xy, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->ws_idx, (size_t)p->N);
-  rc = rc ? rc : dalloc(&p->ws2_xy, (size_t)p->N);
-  rc = rc ? rc : dalloc(&p->ws2_idx, (size_t)p->N);
   rc = rc ? rc : dalloc(&p->set_status, (size_t)VS);
   rc = rc ? rc : dalloc(&p->tile_max, (size_t)p->ntiles);
   rc = rc ? rc : dalloc(&p->group_max, (size_t)p->ngroups * GROUP_STRIDE);
@@ -1629,8 +1649,6 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   A.set_start = p->d_set_start;
   A.ws_xy = p->ws_xy;
   A.ws_idx = p->ws_idx;
-  A.ws2_xy = p->ws2_xy;
-  A.ws2_idx = p->ws2_idx;
   A.set_status = p->set_status;
   A.out_idx = out_idx;
   A.out_counts = out_counts;
