@@ -205,6 +205,7 @@ def main():
                  "seconds": round(time.perf_counter() - t0, 1)}
         log(f"[bench] autotune: strip {args.strip}, fan-in {fan_in} ({tms:.3f} ms)")
     plan = uh.upper_hull_plan_create(off, strip=args.strip, fan_in=fan_in, flags=flags)
+    plan_cfg = plan.config
     out_idx = torch.empty(max(H * N, 1), dtype=torch.int32, device=dev)
     out_cnt = torch.empty(H * S, dtype=torch.int32, device=dev)
     stats = torch.zeros((H * S, 2), dtype=torch.int64, device=dev)
@@ -356,7 +357,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_points": N, "sets": S, "strip": args.strip,
                    "tile_points": 64 * args.strip, "launches_per_step": plan.launches,
-                   "fan_in": fan_in or 256, "autotuned": tuned,
+                   "fan_in": plan_cfg["fan_in"], "autotuned": tuned,
                    "graph": bool(args.graph), "force_fallback": bool(args.force_fallback),
                    "cold_cache": bool(args.flush),
                    "hoods": "upper and lower" if H == 2 else "upper",

@@ -78,7 +78,9 @@ typedef struct {
   int32_t strip;        /* points per lane in the tile kernel's serial     */
                         /* strip hoods: 4, 8, 16 or 32 (0 = default 16)   */
   int32_t fan_in;       /* hoods merged per workgroup in a merge pass:     */
-                        /* 2, 4, ..., 256 (0 = default 256)                */
+                        /* 2, 4, ..., 256 (0 = default: 256, or 128 or 64 */
+                        /* if that is needed for the first merge pass to  */
+                        /* have an item per compute unit)                 */
   uint32_t flags;       /* UH_FLAG_* bits                                  */
 } upper_hull_config;
 
@@ -191,6 +193,10 @@ void upper_hull_plan_destroy(upper_hull_plan *plan);
  */
 int upper_hull_plan_sorted(const upper_hull_plan *plan, const float **sorted_points,
                            const int32_t **perm);
+
+/* The configuration a plan was built with, defaults resolved (strip,
+ * fan_in, flags) into *config. */
+int upper_hull_plan_config(const upper_hull_plan *plan, upper_hull_config *config);
 
 /* Number of kernel launches one run of the plan enqueues (for profiling). */
 int upper_hull_plan_launches(const upper_hull_plan *plan);

@@ -39,7 +39,8 @@ UH_FLAG_UNSORTED = 16
 EXPORTS = (
     "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
-    "upper_hull_plan_set_probe", "upper_hull_plan_sorted", "upper_hull_autotune",
+    "upper_hull_plan_set_probe", "upper_hull_plan_sorted", "upper_hull_plan_config",
+    "upper_hull_autotune",
     "upper_hull_read_reference",
     "upper_hull_bridge", "upper_hull_orient",
 )
@@ -86,6 +87,8 @@ def load_library():
     lib.upper_hull_plan_set_probe.restype = ctypes.c_int
     lib.upper_hull_autotune.argtypes = [p, p, i32, ctypes.c_uint32, i32, p, p, p]
     lib.upper_hull_autotune.restype = ctypes.c_int
+    lib.upper_hull_plan_config.argtypes = [p, p]
+    lib.upper_hull_plan_config.restype = ctypes.c_int
     lib.upper_hull_plan_sorted.argtypes = [p, ctypes.POINTER(p), ctypes.POINTER(p)]
     lib.upper_hull_plan_sorted.restype = ctypes.c_int
     lib.upper_hull_read_reference.argtypes = [p, i64, i32, p, p]
@@ -183,6 +186,13 @@ class Plan:
         _check(load_library().upper_hull_plan_create(
             off.ctypes.data, self.num_sets, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
+
+    @property
+    def config(self) -> dict:
+        """The plan's strip, fan_in and flags, defaults resolved."""
+        c = upper_hull_config()
+        _check(load_library().upper_hull_plan_config(self._h, ctypes.byref(c)))
+        return {"strip": c.strip, "fan_in": c.fan_in, "flags": c.flags}
 
     @property
     def launches(self) -> int:

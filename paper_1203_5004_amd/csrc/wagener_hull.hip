@@ -1443,6 +1443,26 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   }
   if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
   if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
+  if (!(config && config->fan_in)) {
+    // Default fan-in: the largest of 256, 128, 64 that still gives the first
+    // merge pass an item per compute unit.  A single large set in few, large
+    // items would leave most units idle while each item runs its rounds.
+    int cus = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    auto first_items = [&](int f) {
+      int64_t items = 0;
+      for (int32_t s = 0; s < num_sets; ++s) {
+        const int64_t nt = (set_offsets[s + 1] - set_offsets[s] + 64 * K - 1) / (64 * K);
+        if (nt > 1) items += (nt + f - 1) / f;
+      }
+      return items;
+    };
+    while (F > 64 && first_items(F) < cus) F >>= 1;
+  }
   // the sort's positions are 32-bit
   if ((flags & UH_FLAG_UNSORTED) && set_offsets[num_sets] > (int64_t)UINT32_MAX) return UH_ERR_ARG;
 
@@ -1621,6 +1641,14 @@ int upper_hull_plan_sorted(const upper_hull_plan *plan, const float **sorted_poi
   if (!plan || !plan->unsorted || !sorted_points || !perm) return UH_ERR_ARG;
   *sorted_points = (const float *)plan->sorted;
   *perm = plan->perm;
+  return UH_OK;
+}
+
+int upper_hull_plan_config(const upper_hull_plan *plan, upper_hull_config *config) {
+  if (!plan || !config) return UH_ERR_ARG;
+  config->strip = plan->K;
+  config->fan_in = plan->F;
+  config->flags = plan->flags;
   return UH_OK;
 }
 
