@@ -802,22 +802,38 @@ __device__ __forceinline__ void block_excl_max(float v, float all_pre, float all
 // keeping corners [lo[k], lo[k] + cum[k + 1] - cum[k]) of its slot; element
 // e of the block is element c0 + e of the item (cum: exclusive prefix of the
 // kept counts over the item's children, in LDS).
+// With lbase, the children's corner positions are also copied to LDS, child
+// k's from lxy[lbase[k]] on, and the searches read them there.
 struct Rope {
   const float2 *xy;
   const int *cum, *lo;
   int64_t off, stride;
   int k0, k1, c0;
-  // workspace position of the item's element gi (cum[k0] <= gi < cum[k1])
-  __device__ __forceinline__ int64_t where(int gi) const {
+  const float2 *lxy = nullptr;
+  const int *lbase = nullptr;
+  // the child holding the item's element gi (cum[k0] <= gi < cum[k1])
+  __device__ __forceinline__ int child(int gi) const {
     int l = k0, h = k1;
     while (h - l > 1) {
       const int mid = (l + h) >> 1;
       if (cum[mid] <= gi) l = mid;
       else h = mid;
     }
+    return l;
+  }
+  // workspace position of the item's element gi
+  __device__ __forceinline__ int64_t where(int gi) const {
+    const int l = child(gi);
     return off + (int64_t)l * stride + lo[l] + (gi - cum[l]);
   }
-  __device__ __forceinline__ float2 operator[](int e) const { return xy[where(c0 + e)]; }
+  __device__ __forceinline__ float2 operator[](int e) const {
+    const int gi = c0 + e;
+    if (lxy) {
+      const int l = child(gi);
+      return lxy[lbase[l] + lo[l] + (gi - cum[l])];
+    }
+    return xy[where(gi)];
+  }
 };
 
 // One workgroup of BLK threads merges the hoods of up to BLK consecutive
@@ -829,8 +845,12 @@ struct Rope {
 template <int BLK, int VMX>
 __global__ __launch_bounds__(BLK) void merge_kernel(
     RunArgs A, const MergeItem *items, const int32_t *child_cnt, int32_t *cnt_out) {
-  __shared__ float2 bxy[VMX];
-  __shared__ int32_t bid[VMX];
+  // VMX corners (x, y, index) for the LDS path; the global path reuses the
+  // same bytes as 1.5 * VMX corner positions (x, y)
+  __shared__ __attribute__((aligned(16))) char lds_corners[VMX * 12];
+  float2 *const bxy = reinterpret_cast<float2 *>(lds_corners);
+  int32_t *const bid = reinterpret_cast<int32_t *>(lds_corners + VMX * 8);
+  __shared__ int scum[BLK + 1];
   __shared__ int bcnt[BLK];
   __shared__ int soff[BLK];
   __shared__ int2 sblk[BLK];  // LDS path: (base, count) per child block
@@ -1064,9 +1084,26 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   // where they are (Rope), and the result is gathered once at the end.
   if (pts && c > 0)  // point-list children first become hoods, in place
     bcnt[tid] = chain_inplace(A.ws_xy + g, A.ws_idx + g, c, oc, fe);
-  int *cum = bid;            // [BLK + 1] exclusive prefix of the kept counts
-  int *klo = bid + BLK + 1;  // [BLK] start of each child's kept interval
+  int *const cum = scum;                           // [BLK + 1] prefix of the kept counts
+  int *const klo = reinterpret_cast<int *>(sblk);  // [BLK] start of each child's kept interval
   klo[tid] = 0;
+  // If the corners' positions fit in LDS (1.5 * VMX of them), copy them
+  // there: child k's at soff[k] (its count before chaining is an upper bound)
+  const bool in_lds = V <= VMX + VMX / 2;
+  float2 *const lxy = reinterpret_cast<float2 *>(lds_corners);
+  if (in_lds) {
+    __syncthreads();  // the chained counts
+    const int cnt = tid < nch ? bcnt[tid] : 0;
+    for (int e0 = 0; e0 < cnt; e0 += 8) {
+      float2 v8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + u < cnt) v8[u] = A.ws_xy[g + e0 + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e0 + u < cnt) lxy[soff[tid] + e0 + u] = v8[u];
+    }
+  }
   auto rescan = [&]() {
     __syncthreads();
     int tot;
@@ -1087,6 +1124,10 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     if (active) {
       Rope P{A.ws_xy, cum, klo, it.off, it.stride, lp, lq, cum[lp]};
       Rope Q{A.ws_xy, cum, klo, it.off, it.stride, lq, le, cum[lq]};
+      if (in_lds) {
+        P.lxy = Q.lxy = lxy;
+        P.lbase = Q.lbase = soff;
+      }
       int hp = cum[lq] - cum[lp], qs = 0;
       const int hq = cum[le] - cum[lq];
       if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
@@ -1118,7 +1159,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   }
   // the result: corner e lives in child l with cum[l] <= e < cum[l + 1]
   const int hc = cum[BLK];
-  const Rope R{A.ws_xy, cum, klo, it.off, it.stride, 0, nch, 0};
+  const Rope R{A.ws_xy, cum, klo, it.off, it.stride, 0, nch, 0};  // reads the workspace
   if (it.final_) {
     int32_t *dst = A.out_idx + A.set_start[it.set];
     for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {

@@ -133,10 +133,10 @@ def test_sizes_around_tiles(n):
     assert_parity(synth.arc(min(n, 1 << 20), 20, 4, seed=n + 1))
 
 
-def concave_chain(max_step=100):
+def concave_chain(max_step=100, G=20):
     """A strictly concave chain whose every point is a corner: consecutive
     edge vectors are the primitive (dx, dy), 1 <= dx, |dy| <= max_step,
-    in decreasing slope; all coordinates stay below 2^20 (exact float32)."""
+    in decreasing slope; all coordinates stay below 2^G (exact float32)."""
     from math import gcd
     vec = [(dx, dy) for dx in range(1, max_step + 1) for dy in range(-max_step, max_step + 1)
            if gcd(dx, abs(dy)) == 1]
@@ -144,8 +144,8 @@ def concave_chain(max_step=100):
     X = np.concatenate([[0], np.cumsum([v[0] for v in vec])])
     Y = np.concatenate([[0], np.cumsum([v[1] for v in vec])])
     Y = Y - Y.min()
-    assert X.max() < (1 << 20) and Y.max() < (1 << 20)
-    return synth.from_integers(X, Y, 20)
+    assert X.max() < (1 << G) and Y.max() < (1 << G)
+    return synth.from_integers(X, Y, G)
 
 
 def test_concave_all_corners_global_path():
@@ -429,3 +429,18 @@ def test_default_fan_in_fills_the_compute_units():
     assert plan.config["fan_in"] == 256
     plan.close()
     assert uh.upper_hull_plan_create([0, 100], fan_in=16).config["fan_in"] == 16
+
+
+@pytest.mark.parametrize("n", [6000, 7000, 9000, 12000, 20000])
+def test_large_merges_every_point_a_corner(n):
+    # a strictly concave chain: every point is a corner and the last merge
+    # holds all n of them: in LDS (n <= 6144), positions in LDS with the
+    # hoods in the workspace (6144 < n <= 9216), or all in the workspace
+    xy = concave_chain(130, G=24)[:n]
+    c, idx = gpu_hull(xy)
+    assert c == n and np.array_equal(idx, np.arange(n))
+    # the same inside a batch, next to a set that is not concave
+    pts, off = synth.concat_sets([synth.uniform(5000, 20, seed=n), xy, xy[: n // 3]])
+    for fan_in in (0, 4):
+        out, cnt = gpu_batched(pts, off, fan_in=fan_in)
+        assert_batched_equal(pts, off, out, cnt)
