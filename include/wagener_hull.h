@@ -78,8 +78,9 @@ typedef struct {
   int32_t strip;        /* points per lane in the tile kernel's serial     */
                         /* strip hoods: 4, 8, 16 or 32 (0 = default 16)   */
   int32_t fan_in;       /* hoods merged per workgroup in a merge pass:     */
-                        /* 2, 4, ..., 256 (0 = default: 256, or 128 or 64 */
-                        /* if that is needed for the first merge pass to  */
+                        /* 2, 4, ..., 256 (0 = default: 256, or for a  */
+                        /* plan of at least 8 tiles per compute unit 128  */
+                        /* or 64 if needed for the first merge pass to    */
                         /* have an item per compute unit)                 */
   uint32_t flags;       /* UH_FLAG_* bits                                  */
 } upper_hull_config;
@@ -216,7 +217,7 @@ int upper_hull_plan_set_probe(upper_hull_plan *plan, hipEvent_t before,
  * Autotuner: chooses the tile size (T = 64 * strip points) and the number of
  * merge rounds fused per workgroup (log2 fan_in) for a set layout by timing
  * them on the caller's data.  Every (strip, fan_in) pair with strip in
- * {8, 16, 32} and fan_in in {16, 64, 256} runs `reps` times (after one
+ * {8, 16, 32} and fan_in in {16, 32, 64, 128, 256} runs `reps` times (after one
  * untimed run) on `stream` under `flags` (UH_FLAG_GRAPH is ignored); the
  * fastest mean time wins, ties to the earlier pair.  Synchronous: returns
  * when the timing is done.

@@ -1485,9 +1485,11 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
   if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
   if (!(config && config->fan_in)) {
-    // Default fan-in: the largest of 256, 128, 64 that still gives the first
-    // merge pass an item per compute unit.  A single large set in few, large
-    // items would leave most units idle while each item runs its rounds.
+    // Default fan-in: 256; for a plan of at least 8 tiles per compute unit,
+    // the largest of 256, 128, 64 that still gives the first merge pass an
+    // item per compute unit.  A large set in few, large items would leave
+    // most units idle while each item runs its rounds; a small plan keeps
+    // the fewest passes.
     int cus = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1502,7 +1504,11 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       }
       return items;
     };
-    while (F > 64 && first_items(F) < cus) F >>= 1;
+    int64_t tiles = 0;
+    for (int32_t s = 0; s < num_sets; ++s)
+      tiles += (set_offsets[s + 1] - set_offsets[s] + 64 * K - 1) / (64 * K);
+    if (tiles >= 8 * (int64_t)cus)
+      while (F > 64 && first_items(F) < cus) F >>= 1;
   }
   // the sort's positions are 32-bit
   if ((flags & UH_FLAG_UNSORTED) && set_offsets[num_sets] > (int64_t)UINT32_MAX) return UH_ERR_ARG;
@@ -1818,9 +1824,9 @@ int upper_hull_autotune(const float *points, const int64_t *set_offsets,
     rc = UH_ERR_HIP;
   float best_t = -1.0f;
   upper_hull_config chosen = {16, 256, flags};
-  static const int strips[] = {8, 16, 32}, fans[] = {16, 64, 256};
+  static const int strips[] = {8, 16, 32}, fans[] = {16, 32, 64, 128, 256};
   for (int si = 0; si < 3 && !rc; ++si) {
-    for (int fi = 0; fi < 3 && !rc; ++fi) {
+    for (int fi = 0; fi < 5 && !rc; ++fi) {
       const upper_hull_config cfg = {strips[si], fans[fi], flags};
       upper_hull_plan *plan = nullptr;
       rc = upper_hull_plan_create(set_offsets, num_sets, &cfg, &plan);

@@ -279,7 +279,7 @@ def test_autotune_picks_a_candidate_with_identical_results():
             synth.uniform(777, 20, seed=23)]
     pts, off = synth.concat_sets(sets)
     cfg, ms = uh.upper_hull_autotune(_dev(pts), off, reps=2)
-    assert cfg["strip"] in (8, 16, 32) and cfg["fan_in"] in (16, 64, 256)
+    assert cfg["strip"] in (8, 16, 32) and cfg["fan_in"] in (16, 32, 64, 128, 256)
     assert cfg["flags"] == 0 and ms > 0
     out, cnt = gpu_batched(pts, off, strip=cfg["strip"], fan_in=cfg["fan_in"])
     assert_batched_equal(pts, off, out, cnt)
@@ -424,8 +424,11 @@ def test_default_fan_in_fills_the_compute_units():
     assert F in (64, 128, 256)
     assert -(-16384 // F) >= min(cus, 256) or F == 64
     plan.close()
-    # many sets: the default stays 256
+    # many sets: the default stays 256; so does a small single set
     plan = uh.upper_hull_plan_create(np.arange(0, 4097 * 5000, 5000))
+    assert plan.config["fan_in"] == 256
+    plan.close()
+    plan = uh.upper_hull_plan_create([0, 1 << 18])
     assert plan.config["fan_in"] == 256
     plan.close()
     assert uh.upper_hull_plan_create([0, 100], fan_in=16).config["fan_in"] == 16
