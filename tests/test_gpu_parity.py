@@ -447,3 +447,22 @@ def test_large_merges_every_point_a_corner(n):
     for fan_in in (0, 4):
         out, cnt = gpu_batched(pts, off, fan_in=fan_in)
         assert_batched_equal(pts, off, out, cnt)
+
+
+def test_work_per_point_stays_bounded():
+    # The paper's work-optimal variant (its conclusions): serial strip hoods,
+    # then merges with fewer lanes than corners by multi-level bracketing:
+    # O(n) work.  Orientation tests per point must not grow with n, even when
+    # every point is a corner (the concave chain) or on a noisy arc.
+    per = {}
+    for name, make in (("concave", lambda n: concave_chain(130, G=24)[:n]),
+                       ("arc", lambda n: synth.arc(n, 24, 4, seed=n))):
+        for n in (5000, 20000) if name == "concave" else (1 << 16, 1 << 20):
+            xy = make(n)
+            off = np.array([0, len(xy)], np.int64)
+            out, cnt, st = gpu_batched(xy, off, with_stats=True)
+            assert_batched_equal(xy, off, out, cnt)
+            per[(name, n)] = st[0, 0] / len(xy)
+    assert per[("concave", 20000)] <= 1.25 * per[("concave", 5000)] + 0.5, per
+    assert per[("arc", 1 << 20)] <= 1.25 * per[("arc", 1 << 16)] + 0.5, per
+    assert max(per.values()) < 16, per  # measured: about 11.3 (concave), 3.5 to 5 (arc)
