@@ -26,7 +26,7 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off",                       # the predicate's error bound
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-result", "-Wno-unused-value",
+    "-Wall",
 ]
 
 

@@ -1340,23 +1340,23 @@ int upload(T *dst, const std::vector<T> &src) {
 }
 
 void free_plan_memory(upper_hull_plan *p) {
-  hipFree(p->d_set_start);
-  hipFree(p->d_tiles);
-  hipFree(p->d_cnt0);
-  for (auto *q : p->d_items) hipFree(q);
-  for (auto *q : p->d_cnt) hipFree(q);
-  hipFree(p->ws_xy);
-  hipFree(p->ws_idx);
-  hipFree(p->set_status);
-  hipFree(p->tile_max);
-  hipFree(p->group_max);
-  hipFree(p->hull_idx);
-  hipFree(p->hull_cnt);
+  (void)hipFree(p->d_set_start);
+  (void)hipFree(p->d_tiles);
+  (void)hipFree(p->d_cnt0);
+  for (auto *q : p->d_items) (void)hipFree(q);
+  for (auto *q : p->d_cnt) (void)hipFree(q);
+  (void)hipFree(p->ws_xy);
+  (void)hipFree(p->ws_idx);
+  (void)hipFree(p->set_status);
+  (void)hipFree(p->tile_max);
+  (void)hipFree(p->group_max);
+  (void)hipFree(p->hull_idx);
+  (void)hipFree(p->hull_cnt);
   uh_rs::radix_plan_free(&p->rs);
-  hipFree(p->sorted);
-  hipFree(p->perm);
-  for (auto &kv : p->graphs) hipGraphExecDestroy(kv.second);
-  if (p->cap_stream) hipStreamDestroy(p->cap_stream);
+  (void)hipFree(p->sorted);
+  (void)hipFree(p->perm);
+  for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
 }
 
 int enqueue_run(upper_hull_plan *p, const RunArgs &A0, hipStream_t stream) {
@@ -1523,7 +1523,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   if (both)
     for (int32_t s = 0; s < num_sets; ++s) voff.push_back(set_offsets[num_sets] + set_offsets[s + 1]);
   auto *p = new upper_hull_plan();
-  hipGetDevice(&p->device);
+  (void)hipGetDevice(&p->device);
   p->both = both;
   p->in_S = num_sets;
   p->in_N = set_offsets[num_sets];
@@ -1755,12 +1755,12 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
       return UH_ERR_HIP;
     const int rc = enqueue_run(p, A, p->cap_stream);
     if (hipStreamEndCapture(p->cap_stream, &g) != hipSuccess || rc) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return rc ? rc : UH_ERR_HIP;
     }
     hipGraphExec_t ex = nullptr;
     const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (ie != hipSuccess) return UH_ERR_HIP;
     itg = p->graphs.emplace(key, ex).first;
   }
@@ -1770,11 +1770,11 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
 void upper_hull_plan_destroy(upper_hull_plan *plan) {
   if (!plan) return;
   int cur = 0;
-  hipGetDevice(&cur);
-  hipSetDevice(plan->device);
-  hipDeviceSynchronize();
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(plan->device);
+  (void)hipDeviceSynchronize();
   free_plan_memory(plan);
-  hipSetDevice(cur);
+  (void)hipSetDevice(cur);
   delete plan;
 }
 
@@ -1848,10 +1848,10 @@ int upper_hull_autotune(const float *points, const int64_t *set_offsets,
       }
     }
   }
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
-  hipFree(out_idx);
-  hipFree(out_counts);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out_idx);
+  (void)hipFree(out_counts);
   if (rc) return rc;
   *best = chosen;
   if (best_ms) *best_ms = best_t;
