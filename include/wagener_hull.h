@@ -1,5 +1,6 @@
 /*
- * wagener_hull.h -- C ABI of the MI355X (gfx950) upper-hood library.
+ * wagener_hull.h -- C ABI of the MI355X (gfx950) upper-hood / convex-hull
+ * library.
  *
  * The library computes the upper hood (upper convex hull closed by downward
  * vertical rays) of x-sorted planar points with Wagener's merge, following
@@ -9,14 +10,18 @@
  * sampled parallel search (the match-and-merge procedure, steps mam1-mam5)
  * and then keeping the left hood's corners up to the bridge and the right
  * hood's corners from it (mam6).  Everything runs on the device; the host is
- * touched only by the calls below.
+ * touched only by the calls below.  On request the same read of the points
+ * also gives the lower hood (UH_FLAG_BOTH_HOODS; convex_hull joins the two
+ * into the 2-D convex hull the paper's title names), and points in any
+ * order are first sorted by x on the device (UH_FLAG_UNSORTED).
  *
  * Conventions shared by every entry point
  *   - Points are float32 pairs (x, y), interleaved, i.e. the memory layout
  *     of HIP's float2; the pointer must be 8-byte aligned.
  *   - Contract on the data (the paper's problem statement, section
  *     "Wagener's algorithm, CUDA version", plus the readings below):
- *     x non-decreasing in input order; x in [0, 1]; y in [-1, 1]; both
+ *     x non-decreasing in input order (unless UH_FLAG_UNSORTED); x in
+ *     [0, 1]; y in [-1, 1]; both
  *     coordinates multiples of 2^-30 (every float32 in [2^-7, 1] is).  On
  *     such data every orientation sign the library uses is exact.
  *   - Output: the corners of the strict upper hood as 0-based input indices

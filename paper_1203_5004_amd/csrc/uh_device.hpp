@@ -375,25 +375,39 @@ template <class PT, class IT>
 __device__ __forceinline__ int chain_inplace(PT xy, IT id, int n, OrientCount &oc, bool fe) {
   int cnt = 0;
   float2 t1 = make_float2(0.f, 0.f), t2 = t1;  // stack top, second
-  for (int i = 0; i < n; ++i) {
-    const float2 r = xy[i];
-    if (cnt >= 1 && r.x == t1.x) {
-      if (r.y <= t1.y) continue;  // the top hides r
-      --cnt;                      // r hides the top
-      t1 = t2;
-      if (cnt >= 2) t2 = xy[cnt - 2];
+  // points are read eight at a time ahead of the stack's writes, which only
+  // ever go to positions at or below the point being read
+  for (int i0 = 0; i0 < n; i0 += 8) {
+    float2 w8[8];
+    decltype(id[0] + 0) i8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u < n) {
+        w8[u] = xy[i0 + u];
+        i8[u] = id[i0 + u];
+      }
     }
-    while (cnt >= 2 && orient_sign(t2, t1, r, oc, fe) >= 0) {
-      --cnt;  // the top is on or below t2 -> r
-      t1 = t2;
-      if (cnt >= 2) t2 = xy[cnt - 2];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (i0 + u >= n) break;
+      const float2 r = w8[u];
+      if (cnt >= 1 && r.x == t1.x) {
+        if (r.y <= t1.y) continue;  // the top hides r
+        --cnt;                      // r hides the top
+        t1 = t2;
+        if (cnt >= 2) t2 = xy[cnt - 2];
+      }
+      while (cnt >= 2 && orient_sign(t2, t1, r, oc, fe) >= 0) {
+        --cnt;  // the top is on or below t2 -> r
+        t1 = t2;
+        if (cnt >= 2) t2 = xy[cnt - 2];
+      }
+      xy[cnt] = r;
+      id[cnt] = i8[u];
+      t2 = t1;
+      t1 = r;
+      ++cnt;
     }
-    const auto ri = id[i];
-    xy[cnt] = r;
-    id[cnt] = ri;
-    t2 = t1;
-    t1 = r;
-    ++cnt;
   }
   return cnt;
 }

@@ -798,6 +798,19 @@ __device__ __forceinline__ void block_excl_max(float v, float all_pre, float all
   __syncthreads();  // sw may be reused
 }
 
+// The child whose entries [soff[k], soff[k + 1]) hold entry e (0 <= e < the
+// total): the largest k < n with soff[k] <= e (soff is non-decreasing).
+template <int BLK>
+__device__ __forceinline__ int child_of(const int *soff, int n, int e) {
+  int l = 0, h = n;
+  while (h - l > 1) {
+    const int mid = (l + h) >> 1;
+    if (soff[mid] <= e) l = mid;
+    else h = mid;
+  }
+  return l;
+}
+
 // A block of the merge kernel's global path: children k0 .. k1 - 1, child k
 // keeping corners [lo[k], lo[k] + cum[k + 1] - cum[k]) of its slot; element
 // e of the block is element c0 + e of the item (cum: exclusive prefix of the
@@ -937,22 +950,33 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         }
       }
     }
-    if (tid < nch) {
-      for (int e0 = known_max ? 0 : PRE; e0 < c; e0 += 8) {
-        float2 vx[8];
-        int32_t vi[8];
+    // the rest: every thread copies a share of all V entries, eight loads in
+    // flight, so one large child does not keep a single thread busy
+    {
+      const int skip = known_max ? 0 : PRE;  // entries prefetched above
+      for (int e0 = 0; e0 < V; e0 += 8 * BLK) {
+        float2 vx8[8];
+        int32_t vi8[8];
+        int dst[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          if (e0 + u < c) {
-            vx[u] = A.ws_xy[g + e0 + u];
-            vi[u] = A.ws_idx[g + e0 + u];
+          const int e = e0 + u * BLK + tid;
+          dst[u] = -1;
+          if (e < V) {
+            const int k = child_of<BLK>(soff, nch, e), j = e - soff[k];
+            if (j >= skip) {
+              const int64_t src = it.off + (int64_t)k * it.stride + j;
+              vx8[u] = A.ws_xy[src];
+              vi8[u] = A.ws_idx[src];
+              dst[u] = e;
+            }
           }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          if (e0 + u < c) {
-            bxy[o + e0 + u] = vx[u];
-            bid[o + e0 + u] = vi[u];
+          if (dst[u] >= 0) {
+            bxy[dst[u]] = vx8[u];
+            bid[dst[u]] = vi8[u];
           }
         }
       }
@@ -1093,15 +1117,24 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   float2 *const lxy = reinterpret_cast<float2 *>(lds_corners);
   if (in_lds) {
     __syncthreads();  // the chained counts
-    const int cnt = tid < nch ? bcnt[tid] : 0;
-    for (int e0 = 0; e0 < cnt; e0 += 8) {
+    for (int e0 = 0; e0 < V; e0 += 8 * BLK) {  // shared by all threads
       float2 v8[8];
+      int dst[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * BLK + tid;
+        dst[u] = -1;
+        if (e < V) {
+          const int k = child_of<BLK>(soff, nch, e), j = e - soff[k];
+          if (j < bcnt[k]) {
+            v8[u] = A.ws_xy[it.off + (int64_t)k * it.stride + j];
+            dst[u] = e;
+          }
+        }
+      }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (e0 + u < cnt) v8[u] = A.ws_xy[g + e0 + u];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (e0 + u < cnt) lxy[soff[tid] + e0 + u] = v8[u];
+        if (dst[u] >= 0) lxy[dst[u]] = v8[u];
     }
   }
   auto rescan = [&]() {
