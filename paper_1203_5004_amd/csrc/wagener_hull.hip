@@ -1517,18 +1517,25 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   }
   if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
   if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
+  // a large plan: at least 8 tiles per compute unit
+  int cus = 0;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  int64_t all_tiles = 0;
+  for (int32_t s = 0; s < num_sets; ++s)
+    all_tiles += (set_offsets[s + 1] - set_offsets[s] + 64 * K - 1) / (64 * K);
+  const bool large_plan = all_tiles >= 8 * (int64_t)cus;
   if (!(config && config->fan_in)) {
     // Default fan-in: 256; for a plan of at least 8 tiles per compute unit,
     // the largest of 256, 128, 64 that still gives the first merge pass an
     // item per compute unit.  A large set in few, large items would leave
     // most units idle while each item runs its rounds; a small plan keeps
     // the fewest passes.
-    int cus = 0;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
     auto first_items = [&](int f) {
       int64_t items = 0;
       for (int32_t s = 0; s < num_sets; ++s) {
@@ -1537,10 +1544,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       }
       return items;
     };
-    int64_t tiles = 0;
-    for (int32_t s = 0; s < num_sets; ++s)
-      tiles += (set_offsets[s + 1] - set_offsets[s] + 64 * K - 1) / (64 * K);
-    if (tiles >= 8 * (int64_t)cus)
+    if (large_plan)
       while (F > 64 && first_items(F) < cus) F >>= 1;
   }
   // the sort's positions are 32-bit
@@ -1686,7 +1690,10 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     p->d_items.push_back(di);
     p->d_cnt.push_back(dcnt);
     p->pass_items.push_back((int32_t)items.size());
-    bool wide = false;
+    // the wide workgroup (twice the threads and the LDS, one per compute
+    // unit) for more than BLOCK children, and in a large plan for a pass of
+    // few items, whose merges are large and latency-bound
+    bool wide = large_plan && items.size() <= 64;
     for (const MergeItem &m : items) wide = wide || m.nch > BLOCK;
     p->pass_wide.push_back(wide);
   }
