@@ -150,3 +150,21 @@ def test_sorted_view_needs_an_unsorted_plan():
     with pytest.raises(RuntimeError):
         plan.sorted_view()
     plan.close()
+
+
+def test_unsorted_edge_values():
+    good = _shuffled_sets(80, sizes=[3000])[0]
+    # NaN and negative x are data errors wherever the sort puts them
+    for v in (np.nan, -0.25, 1.5):
+        bad = good.copy()
+        bad[17, 0] = v
+        plan, pts, off, out, cnt = run_plan([bad], uh.UH_FLAG_UNSORTED)
+        assert cnt[0] == uh.UH_ERR_RANGE, v
+        plan.close()
+    # -0.0 is the same x as +0.0 (and sorts with it, in input order)
+    z = good.copy()
+    z[:40, 0] = 0.0
+    z[5:40:3, 0] = -0.0
+    plan, pts, off, out, cnt = run_plan([z], uh.UH_FLAG_UNSORTED | uh.UH_FLAG_BOTH_HOODS)
+    check_hoods([z], off, out, cnt, both=True)
+    plan.close()
