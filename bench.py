@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "input points/sec (upper hull, 1 GPU) + % HBM roofline; batched vs plain"
 KERNEL_SOURCES = ["paper_1203_5004_amd/csrc/wagener_hull.hip",
                   "paper_1203_5004_amd/csrc/uh_device.hpp"]
+HOST_MARKER = "// " + "=" * 70 + " host"
 
 
 def log(*a):
@@ -33,13 +34,14 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    """Hash of the kernel sources' code (comments and whitespace removed), so
-    that a counter summary stays attached to the code it was measured on."""
+    """Hash of the device code (comments and whitespace removed; the host
+    part of the library source after its host marker is left out), so that a
+    counter summary stays attached to the kernels it was measured on."""
     import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel)) as fh:
-            src = fh.read()
+            src = fh.read().split(HOST_MARKER)[0]
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
         src = re.sub(r"//[^\n]*", " ", src)
         h.update(" ".join(src.split()).encode())

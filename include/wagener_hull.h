@@ -187,6 +187,20 @@ int upper_hull_plan_run(upper_hull_plan *plan, const float *points,
                         int32_t *out_idx, int32_t *out_counts,
                         upper_hull_stats *stats, hipStream_t stream);
 
+/*
+ * Batched call without a plan object: upper hoods of all sets
+ * points[set_offsets[s] .. set_offsets[s+1]) in one device-resident run,
+ * with the default configuration.  Arguments and output layout as for
+ * upper_hull_plan_create (set_offsets on the HOST) and upper_hull_plan_run.
+ * The library keeps a plan per distinct set layout (a few, least recently
+ * created dropped first), built on first use: not while `stream` is
+ * capturing (UH_ERR_CAPTURE).  Calls with the same layout share that plan's
+ * workspace, so calls on different streams must not overlap.
+ */
+int upper_hull_batched(const float *points, const int64_t *set_offsets, int32_t num_sets,
+                       int32_t *out_idx, int32_t *out_counts, upper_hull_stats *stats,
+                       hipStream_t stream);
+
 /* Free a plan and its device memory (synchronises its device first). */
 void upper_hull_plan_destroy(upper_hull_plan *plan);
 

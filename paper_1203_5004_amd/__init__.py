@@ -37,7 +37,8 @@ UH_FLAG_BOTH_HOODS = 8
 UH_FLAG_UNSORTED = 16
 
 EXPORTS = (
-    "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_plan_create",
+    "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_batched",
+    "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
     "upper_hull_plan_set_probe", "upper_hull_plan_sorted", "upper_hull_plan_config",
     "upper_hull_autotune",
@@ -75,6 +76,8 @@ def load_library():
     lib.upper_hull.restype = ctypes.c_int
     lib.convex_hull.argtypes = [p, i64, p, p, p]
     lib.convex_hull.restype = ctypes.c_int
+    lib.upper_hull_batched.argtypes = [p, p, i32, p, p, p, p]
+    lib.upper_hull_batched.restype = ctypes.c_int
     lib.upper_hull_plan_create.argtypes = [p, i32, p, ctypes.POINTER(p)]
     lib.upper_hull_plan_create.restype = ctypes.c_int
     lib.upper_hull_plan_run.argtypes = [p, p, p, p, p, p]
@@ -167,6 +170,34 @@ def _single(name, points, out_idx, out_count, stream):
     _check(getattr(load_library(), name)(_ptr(points), n, _ptr(out_idx), _ptr(out_count),
                                          _stream(stream)))
     return out_idx, out_count
+
+
+def upper_hull_batched(points, set_offsets, out_idx=None, out_counts=None, stats=None,
+                       stream=None):
+    """Upper hoods of every set (host offsets, len S + 1) with a cached plan.
+    Returns (out_idx int32[N], out_counts int32[S]); set s's corners are at
+    out_idx[offsets[s]:offsets[s] + out_counts[s]]."""
+    torch = _torch()
+    _dev_tensor(points, torch.float32, "points")
+    off = np.ascontiguousarray(np.asarray(set_offsets, dtype=np.int64))
+    S, N = off.shape[0] - 1, int(off[-1])
+    if S < 1 or points.numel() != 2 * N:
+        raise ValueError("points do not match set_offsets")
+    if out_idx is None:
+        out_idx = torch.empty(max(N, 1), dtype=torch.int32, device=points.device)
+    if out_counts is None:
+        out_counts = torch.empty(S, dtype=torch.int32, device=points.device)
+    _dev_tensor(out_idx, torch.int32, "out_idx")
+    _dev_tensor(out_counts, torch.int32, "out_counts")
+    if out_idx.numel() < N or out_counts.numel() < S:
+        raise ValueError("output buffers too small")
+    if stats is not None:
+        _dev_tensor(stats, torch.int64, "stats")
+        if stats.numel() < 2 * S:
+            raise ValueError("stats needs 2 int64 per set")
+    _check(load_library().upper_hull_batched(_ptr(points), off.ctypes.data, S, _ptr(out_idx),
+                                             _ptr(out_counts), _ptr(stats), _stream(stream)))
+    return out_idx, out_counts
 
 
 class Plan:

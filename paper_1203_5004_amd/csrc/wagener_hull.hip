@@ -1445,6 +1445,8 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A0, hipStream_t stream) {
 
 std::mutex g_cache_mu;
 std::map<std::tuple<int, int64_t, uint32_t>, upper_hull_plan *> g_single_plans;
+// batched calls without a plan: one cached plan per (device, set layout)
+std::map<std::pair<int, std::vector<int64_t>>, upper_hull_plan *> g_batched_plans;
 
 // The cached single-set plan for n points on the current device (flags:
 // UH_FLAG_BOTH_HOODS for the convex hull, which also gets its buffers).
@@ -1842,6 +1844,35 @@ int convex_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_c
   hipLaunchKernelGGL(hull_assemble_kernel, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256),
                      0, stream, p->hull_idx, p->hull_cnt, n, out_idx, out_count);
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+int upper_hull_batched(const float *points, const int64_t *set_offsets, int32_t num_sets,
+                       int32_t *out_idx, int32_t *out_counts, upper_hull_stats *stats,
+                       hipStream_t stream) {
+  if (!set_offsets || num_sets < 1 || !out_counts) return UH_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
+  upper_hull_plan *p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto key = std::make_pair(dev, std::vector<int64_t>(set_offsets, set_offsets + num_sets + 1));
+    auto it = g_batched_plans.find(key);
+    if (it != g_batched_plans.end()) {
+      p = it->second;
+    } else {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
+      if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
+      if (g_batched_plans.size() >= 8) {  // bounded cache: drop the oldest
+        upper_hull_plan_destroy(g_batched_plans.begin()->second);
+        g_batched_plans.erase(g_batched_plans.begin());
+      }
+      const int rc = upper_hull_plan_create(set_offsets, num_sets, nullptr, &p);
+      if (rc) return rc;
+      g_batched_plans.emplace(std::move(key), p);
+    }
+  }
+  return upper_hull_plan_run(p, points, out_idx, out_counts, stats, stream);
 }
 
 int upper_hull_autotune(const float *points, const int64_t *set_offsets,

@@ -466,3 +466,19 @@ def test_work_per_point_stays_bounded():
     assert per[("concave", 20000)] <= 1.25 * per[("concave", 5000)] + 0.5, per
     assert per[("arc", 1 << 20)] <= 1.25 * per[("arc", 1 << 16)] + 0.5, per
     assert max(per.values()) < 16, per  # measured: about 11.3 (concave), 3.5 to 5 (arc)
+
+
+def test_batched_call_without_a_plan():
+    sets = [synth.uniform(9000, 20, seed=91), np.zeros((0, 2), np.float32),
+            synth.arc(5000, 20, 4, seed=92), synth.lattice_points(30, 8, seed=93)]
+    pts, off = synth.concat_sets(sets)
+    d = _dev(pts)
+    for _ in range(2):  # the second call reuses the cached plan
+        out, cnt = uh.upper_hull_batched(d, off)
+        torch.cuda.synchronize()
+        assert_batched_equal(pts, off, out.cpu().numpy(), cnt.cpu().numpy())
+    stats = torch.zeros((len(off) - 1, 2), dtype=torch.int64, device="cuda")
+    out, cnt = uh.upper_hull_batched(d, off, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy()
+    assert np.all(st[:, 1] <= st[:, 0])
