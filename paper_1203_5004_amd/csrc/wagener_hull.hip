@@ -22,8 +22,14 @@
 //                 one-tile set).
 //   merge_kernel  one workgroup merges up to F consecutive hoods of the
 //                 previous level of one set through log2(F) further rounds,
-//                 in LDS when they fit, else in place in the workspace.
-//                 Repeated until every set has a single hood.
+//                 in LDS when they fit, else over the workspace by
+//                 narrowing each child's kept interval.  Repeated until
+//                 every set has a single hood.
+//
+// With both hoods the tile kernel also builds, from the same registers, the
+// lower hood (the upper hood of the mirrored points) into a second half of
+// the schedule; points in any order first go through the device sort in
+// radix_sort.hip, and unsort_kernel maps the corners back to input indices.
 //
 // Hoods are stored compactly (no REMOTE padding): a block's corners are a
 // prefix of its slot, with a count.  The workspace holds, at each point's
