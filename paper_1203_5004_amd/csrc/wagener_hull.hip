@@ -804,6 +804,41 @@ __device__ __forceinline__ void block_excl_max(float v, float all_pre, float all
   __syncthreads();  // sw may be reused
 }
 
+// Segmented exclusive scan over the threads of a workgroup, in thread order:
+// thread t brings (head, v), head meaning that a segment starts inside its
+// chunk (v then covers only its chunk after the last start).  Returns the
+// combination by op of the earlier threads' values back to the nearest start
+// (ident if none); meaningful for a thread whose chunk continues a segment.
+template <int BLK, class T, class OP>
+__device__ __forceinline__ T seg_excl_scan(bool head, T v, T ident, OP op, T *sv, int *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bool h = head;
+  T x = v;
+  for (int o = 1; o < 64; o <<= 1) {  // inclusive, within the wave
+    const T x2 = __shfl_up(x, o, 64);
+    const bool h2 = __shfl_up((int)h, o, 64) != 0;
+    if (lane >= o) {
+      x = h ? x : op(x2, x);
+      h = h || h2;
+    }
+  }
+  if (lane == 63) {
+    sv[w] = x;
+    sh[w] = h;
+  }
+  __syncthreads();
+  T carry = ident;  // earlier waves, back to the nearest start
+  for (int q = 0; q < w; ++q) carry = sh[q] ? sv[q] : op(carry, sv[q]);
+  __syncthreads();  // sv, sh may be reused
+  T xe = __shfl_up(x, 1, 64);  // exclusive within the wave
+  bool he = __shfl_up((int)h, 1, 64) != 0;
+  if (lane == 0) {
+    xe = ident;
+    he = false;
+  }
+  return he ? xe : op(carry, xe);
+}
+
 // The child whose entries [soff[k], soff[k + 1]) hold entry e (0 <= e < the
 // total): the largest k < n with soff[k] <= e (soff is non-decreasing).
 template <int BLK>
@@ -1008,25 +1043,122 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         block_excl_max<BLK>(cmax, -2.0f, -2.0f, pre, suf, sw4);
       }
       int kept = 0;
-      for (int e0 = 0; e0 < c; e0 += 8) {  // a batch is read before it is rewritten
-        float2 qv[8];
-        int32_t iv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (e0 + u < c) {
-            qv[u] = bxy[o + e0 + u];
-            iv[u] = bid[o + e0 + u];
+      if (__syncthreads_or(c > 256)) {
+        // Some child is large (an arc's steep end tiles, where nearly every
+        // point is a corner): the filter is shared by all threads, thread t
+        // taking entries [t * J, t * J + J) of the V gathered ones.  An entry
+        // needs the highest earlier entry of its own child (a segmented
+        // prefix maximum over the threads) and, if kept, its rank among its
+        // child's kept entries (a segmented prefix sum); then the kept
+        // entries move to the front of their child's segment.
+        float *const fpre = reinterpret_cast<float *>(sres);  // [BLK] per child
+        float *const fsuf = reinterpret_cast<float *>(scum);  // [BLK] per child
+        __shared__ float fsv[BLK / 64];
+        __shared__ int fsi[BLK / 64], fsh[BLK / 64];
+        if (tid < nch) {
+          fpre[tid] = pre;
+          fsuf[tid] = suf;
+        }
+        bcnt[tid] = 0;  // kept per child, filled below
+        __syncthreads();
+        constexpr int J = (VMX + BLK - 1) / BLK;
+        const int e0 = tid * J;
+        const int k0 = e0 < V ? child_of<BLK>(soff, nch, e0) : 0;
+        const bool starts = e0 < V && soff[k0] == e0;  // the chunk starts a child
+        bool head = false;
+        float m = -INFINITY;
+        {
+          int k = k0;
+          for (int j = 0; j < J && e0 + j < V; ++j) {
+            const int e = e0 + j;
+            while (k + 1 < nch && soff[k + 1] <= e) ++k;
+            const float y = bxy[e].y;
+            if (soff[k] == e) {
+              head = true;
+              m = y;
+            } else {
+              m = fmaxf(m, y);
+            }
           }
         }
+        const float mcarry = seg_excl_scan<BLK, float>(
+            head, m, -INFINITY, [](float a, float b) { return fmaxf(a, b); }, fsv, fsh);
+        uint32_t keepbits = 0;
+        int nkept = 0;
+        bool khead = false;
+        {
+          int k = k0;
+          float run = starts ? -INFINITY : mcarry;
+          for (int j = 0; j < J && e0 + j < V; ++j) {
+            const int e = e0 + j;
+            while (k + 1 < nch && soff[k + 1] <= e) ++k;
+            if (soff[k] == e) {
+              run = -INFINITY;
+              khead = true;
+              nkept = 0;
+            }
+            const float y = bxy[e].y;
+            if (y > fmaxf(fpre[k], run) || y >= fsuf[k]) {
+              keepbits |= 1u << j;
+              ++nkept;
+            }
+            run = fmaxf(run, y);
+          }
+        }
+        const int rcarry = seg_excl_scan<BLK, int>(
+            khead, nkept, 0, [](int a, int b) { return a + b; }, fsi, fsh);
+        float2 qv[J];
+        int32_t iv[J];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (e0 + u < c) {
-            const bool keep = qv[u].y > pre || qv[u].y >= suf;
-            pre = fmaxf(pre, qv[u].y);
-            if (keep) {
-              bxy[o + kept] = qv[u];
-              bid[o + kept] = iv[u];
-              ++kept;
+        for (int j = 0; j < J; ++j) {
+          if (e0 + j < V) {
+            qv[j] = bxy[e0 + j];
+            iv[j] = bid[e0 + j];
+          }
+        }
+        __syncthreads();  // every entry is read before any moves
+        {
+          int k = k0;
+          int r = starts ? 0 : rcarry;
+#pragma unroll
+          for (int j = 0; j < J; ++j) {
+            const int e = e0 + j;
+            if (e < V) {
+              while (k + 1 < nch && soff[k + 1] <= e) ++k;
+              if (soff[k] == e) r = 0;
+              if ((keepbits >> j) & 1u) {
+                bxy[soff[k] + r] = qv[j];
+                bid[soff[k] + r] = iv[j];
+                ++r;
+                atomicMax(&bcnt[k], r);
+              }
+            }
+          }
+        }
+        __syncthreads();
+        kept = tid < nch ? bcnt[tid] : 0;
+      } else {
+        // each thread filters its own child in place
+        for (int e0 = 0; e0 < c; e0 += 8) {  // a batch is read before it is rewritten
+          float2 qv[8];
+          int32_t iv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (e0 + u < c) {
+              qv[u] = bxy[o + e0 + u];
+              iv[u] = bid[o + e0 + u];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (e0 + u < c) {
+              const bool keep = qv[u].y > pre || qv[u].y >= suf;
+              pre = fmaxf(pre, qv[u].y);
+              if (keep) {
+                bxy[o + kept] = qv[u];
+                bid[o + kept] = iv[u];
+                ++kept;
+              }
             }
           }
         }
