@@ -86,37 +86,74 @@ class HipEvents:
         self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def cpu_baseline(pts_np, off, budget_s: float, both: bool = False, unsorted: bool = False):
-    """The oracle over the whole workload, repeated until budget_s; with both,
-    the upper and the lower hood of every set (outputs laid out as the
-    library's two halves); with unsorted, a stable sort of every set by x in
-    front and the corners mapped back to input indices."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_threads() -> int:
+    """Host threads the all-cores oracle uses: the CPUs this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, 16))
+
+
+def cpu_baseline(pts_np, off, budget_s: float, threads: int, lib, both: bool = False,
+                 unsorted: bool = False):
+    """The oracle over the whole workload, repeated until budget_s, on `threads`
+    threads (1: the single chain; more: chunks cut at equal-x runs for one set,
+    whole sets per thread for a batch).  With both, the upper and the lower hood
+    of every set (outputs laid out as the library's two halves); with unsorted,
+    a stable sort of every set by x in front (numpy, one thread) and the corners
+    mapped back to input indices."""
     import numpy as np
     import oracle
     t_total, reps = 0.0, 0
     out = cnt = None
-    N = len(pts_np)
+    N, S = len(pts_np), len(off) - 1
+
+    def hoods(src, lower):
+        if threads == 1:
+            fn = oracle.lower_hull_batched if lower else oracle.upper_hull_batched
+            return fn(src, off, lib=lib)
+        if S == 1:
+            rc, idx = oracle.hood_mt(src, threads, lower=lower, lib=lib)
+            o = np.zeros(max(N, 1), np.int32)
+            o[:len(idx)] = idx
+            return o, np.array([rc if rc else len(idx)], np.int64)
+        _, o, c = oracle.hood_batched_mt(src, off, threads, lower=lower, lib=lib)
+        return o, c
+
     while reps < 1 or t_total < budget_s:
         t0 = time.perf_counter()
         src, perm = pts_np, None
         if unsorted:
             perm = np.concatenate([off[s] + oracle.sort_order(pts_np[off[s]:off[s + 1]])
-                                   for s in range(len(off) - 1)] or [np.zeros(0, np.int64)])
+                                   for s in range(S)] or [np.zeros(0, np.int64)])
             src = pts_np[perm]
-        out, cnt = oracle.upper_hull_batched(src, off)
+        out, cnt = hoods(src, False)
         if both:
-            lo, lcnt = oracle.lower_hull_batched(src, off)
-            out, cnt = np.concatenate([out[:N], lo]), np.concatenate([cnt, lcnt])
+            lo, lcnt = hoods(src, True)
+            out, cnt = np.concatenate([out[:N], lo[:N]]), np.concatenate([cnt, lcnt])
         if unsorted:  # sorted positions -> set-relative input indices
             H = 2 if both else 1
             for h in range(H):
-                for s in range(len(off) - 1):
+                for s in range(S):
                     a = h * N + off[s]
-                    c = int(cnt[h * (len(off) - 1) + s])
+                    c = int(cnt[h * S + s])
                     out[a:a + c] = perm[off[s] + out[a:a + c]] - off[s]
         t_total += time.perf_counter() - t0
         reps += 1
-    return len(pts_np) * reps / t_total, reps, t_total, out, cnt
+    return N * reps / t_total, reps, t_total, out, cnt
 
 
 def main():
@@ -132,7 +169,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="choose strip and fan-in by the library's autotuner on this workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=16.0,
+                    help="seconds of oracle timing, split between one thread and all")
     ap.add_argument("--compare-plain", action="store_true",
                     help="also time the plain per-set method (one plan per set, launched "
                          "set by set from the host) against the batched plan")
@@ -337,20 +375,34 @@ def main():
     cpu = None
     checked = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle ...")
-        rate, reps, secs, ref_out, ref_cnt = cpu_baseline(pts_np, off, args.cpu_budget,
-                                                          both=args.both_hoods,
-                                                          unsorted=args.unsorted)
-        cpu = {"value": round(rate, 1), "unit": "points/s", "cores": 1, "kind": "oracle",
-               "sample": f"whole workload ({N} points, {S} sets"
-                         f"{', both hoods' if H == 2 else ''}"
-                         f"{', sorted by x first' if args.unsorted else ''}), {reps} run(s), "
-                         f"{secs:.1f} s, single thread"}
+        import oracle
+        import tempfile
+        lib = oracle.load_native(tempfile.mkdtemp(prefix="uh_oracle_"))
+        threads = cpu_threads()
+        what = (f"whole workload ({N} points, {S} sets"
+                f"{', both hoods' if H == 2 else ''}"
+                f"{', sorted by x first (numpy, one thread)' if args.unsorted else ''})")
+        log(f"[bench] timing the CPU oracle (-O3 -march=native) on 1 and {threads} threads ...")
+        rate1, reps1, secs1, ref_out, ref_cnt = cpu_baseline(
+            pts_np, off, args.cpu_budget / 2, 1, lib, both=args.both_hoods,
+            unsorted=args.unsorted)
+        rate, reps, secs, mt_out, mt_cnt = cpu_baseline(
+            pts_np, off, args.cpu_budget / 2, threads, lib, both=args.both_hoods,
+            unsorted=args.unsorted)
         got = out_idx.cpu().numpy()
         voff = np.concatenate([off[:-1] + h * N for h in range(H)])  # start of every output set
         checked = bool(np.array_equal(cnt_np, ref_cnt.astype(np.int32)) and all(
             np.array_equal(got[a:a + c], ref_out[a:a + c]) for a, c in zip(voff, cnt_np)))
-        log(f"[bench] oracle {rate:.4g} points/s; GPU result equals oracle: {checked}")
+        mt_same = bool(np.array_equal(mt_cnt, ref_cnt) and all(
+            np.array_equal(mt_out[a:a + c], ref_out[a:a + c]) for a, c in zip(voff, cnt_np)))
+        cpu = {"value": round(rate, 1), "unit": "points/s", "cores": threads, "kind": "oracle",
+               "sample": f"{what}: {reps} run(s) in {secs:.1f} s on {threads} threads; "
+                         f"{reps1} run(s) in {secs1:.1f} s on one thread",
+               "single_thread_value": round(rate1, 1), "threads_equal_single": mt_same,
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+               "build": "gcc -O3 -march=native"}
+        log(f"[bench] oracle {rate1:.4g} points/s (1 thread), {rate:.4g} ({threads} threads); "
+            f"GPU result equals oracle: {checked}")
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,

@@ -40,16 +40,53 @@ ERR_GRID = -12
 _lib = None
 
 
+def _compile(out: str, extra: list[str]) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O3", *extra, "-std=gnu11", "-shared", "-fPIC",
+                           "-Wall", "-Werror", _SRC, "-o", tmp, "-lm", "-lpthread"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into oracle/_build/liboracle_hull.so."""
+    """Compile the oracle with gcc into oracle/_build/liboracle_hull.so
+    (portable code: the library also runs on other hosts)."""
     os.makedirs(_BUILD, exist_ok=True)
     if force or not os.path.exists(_LIB_PATH) or (
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC",
-                               "-Wall", "-Werror", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+        _compile(_LIB_PATH, [])
     return _LIB_PATH
+
+
+def build_native(directory: str) -> str:
+    """Compile the oracle with -O3 -march=native for the CPU this runs on, into
+    `directory` (for the CPU baseline's timing; a library built for one CPU
+    may not run on another, so it is built where it is timed)."""
+    os.makedirs(directory, exist_ok=True)
+    out = os.path.join(directory, "liboracle_hull_native.so")
+    _compile(out, ["-march=native"])
+    return out
+
+
+def _declare(lib):
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_upper_hull.argtypes = [p, i64, p, p]
+    lib.oracle_upper_hull.restype = ctypes.c_int
+    lib.oracle_upper_hull_batched.argtypes = [p, p, i64, p, p]
+    lib.oracle_upper_hull_batched.restype = ctypes.c_int
+    for name in ("oracle_lower_hull", "oracle_convex_hull"):
+        getattr(lib, name).argtypes = [p, i64, p, p]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.oracle_lower_hull_batched.argtypes = [p, p, i64, p, p]
+    lib.oracle_lower_hull_batched.restype = ctypes.c_int
+    lib.oracle_orient_signs.argtypes = [p, p, p, i64, p]
+    lib.oracle_orient_signs.restype = ctypes.c_int
+    lib.oracle_hood_mt.argtypes = [p, i64, i32, i32, p, p]
+    lib.oracle_hood_mt.restype = ctypes.c_int
+    lib.oracle_hood_batched_mt.argtypes = [p, p, i64, i32, i32, p, p]
+    lib.oracle_hood_batched_mt.restype = ctypes.c_int
+    lib.oracle_online_cpus.argtypes = []
+    lib.oracle_online_cpus.restype = ctypes.c_int32
+    return lib
 
 
 def _load():
@@ -58,21 +95,14 @@ def _load():
         if not os.path.exists(_LIB_PATH) or (
                 os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
             build(force=True)
-        lib = ctypes.CDLL(_LIB_PATH)
-        i64, p = ctypes.c_int64, ctypes.c_void_p
-        lib.oracle_upper_hull.argtypes = [p, i64, p, p]
-        lib.oracle_upper_hull.restype = ctypes.c_int
-        lib.oracle_upper_hull_batched.argtypes = [p, p, i64, p, p]
-        lib.oracle_upper_hull_batched.restype = ctypes.c_int
-        for name in ("oracle_lower_hull", "oracle_convex_hull"):
-            getattr(lib, name).argtypes = [p, i64, p, p]
-            getattr(lib, name).restype = ctypes.c_int
-        lib.oracle_lower_hull_batched.argtypes = [p, p, i64, p, p]
-        lib.oracle_lower_hull_batched.restype = ctypes.c_int
-        lib.oracle_orient_signs.argtypes = [p, p, p, i64, p]
-        lib.oracle_orient_signs.restype = ctypes.c_int
-        _lib = lib
+        _lib = _declare(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def load_native(directory: str):
+    """The -march=native build (see build_native), loaded separately from the
+    portable one; it exposes the same functions."""
+    return _declare(ctypes.CDLL(build_native(directory)))
 
 
 def _pts(xy) -> np.ndarray:
@@ -129,28 +159,29 @@ def convex_hull(xy) -> np.ndarray:
     return idx
 
 
-def _batched(name, xy, offsets):
+def _batched(name, xy, offsets, lib=None):
     a = _pts(xy)
     off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     S = off.shape[0] - 1
     out = np.zeros(max(a.shape[0], 1), dtype=np.int32)
     counts = np.zeros(max(S, 1), dtype=np.int64)
-    rc = getattr(_load(), name)(a.ctypes.data, off.ctypes.data, S,
-                                out.ctypes.data, counts.ctypes.data)
+    rc = getattr(_lib_or(lib), name)(a.ctypes.data, off.ctypes.data, S,
+                                     out.ctypes.data, counts.ctypes.data)
     if rc != OK:
         raise ValueError(f"oracle: invalid input (status {rc})")
     return out, counts[:S]
 
 
-def upper_hull_batched(xy, offsets):
+def upper_hull_batched(xy, offsets, lib=None):
     """Per-set hulls.  Returns (out_idx, counts): set s's corner indices,
-    relative to offsets[s], are out_idx[offsets[s] : offsets[s] + counts[s]]."""
-    return _batched("oracle_upper_hull_batched", xy, offsets)
+    relative to offsets[s], are out_idx[offsets[s] : offsets[s] + counts[s]].
+    `lib`: another build of the same source (``load_native``)."""
+    return _batched("oracle_upper_hull_batched", xy, offsets, lib)
 
 
-def lower_hull_batched(xy, offsets):
+def lower_hull_batched(xy, offsets, lib=None):
     """Per-set lower hoods, laid out as in ``upper_hull_batched``."""
-    return _batched("oracle_lower_hull_batched", xy, offsets)
+    return _batched("oracle_lower_hull_batched", xy, offsets, lib)
 
 
 def orient_signs(a, b, c) -> np.ndarray:
@@ -185,3 +216,38 @@ def unsorted_hull(xy, hood: str = "upper"):
           "convex": convex_hull_status}[hood]
     rc, idx = fn(a[order])
     return rc, order[idx].astype(np.int32)
+
+
+def _lib_or(lib):
+    return lib if lib is not None else _load()
+
+
+def hood_mt(xy, threads: int, lower: bool = False, lib=None):
+    """(status, indices) of the upper (or lower) hood computed on `threads`
+    threads: chunks cut at equal-x run boundaries, a chain per chunk, then one
+    chain over the chunk hoods.  Same result and status as the single chain."""
+    a = _pts(xy)
+    n = a.shape[0]
+    out = np.empty(max(n, 1), dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    rc = _lib_or(lib).oracle_hood_mt(a.ctypes.data, n, int(threads), int(bool(lower)),
+                                     out.ctypes.data, ctypes.addressof(cnt))
+    return rc, out[: cnt.value].copy()
+
+
+def hood_batched_mt(xy, offsets, threads: int, lower: bool = False, lib=None):
+    """Per-set hoods on `threads` threads (sets taken in order as threads become
+    free); (status, out_idx, counts) laid out as ``upper_hull_batched``."""
+    a = _pts(xy)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    S = off.shape[0] - 1
+    out = np.zeros(max(a.shape[0], 1), dtype=np.int32)
+    counts = np.zeros(max(S, 1), dtype=np.int64)
+    rc = _lib_or(lib).oracle_hood_batched_mt(a.ctypes.data, off.ctypes.data, S, int(threads),
+                                             int(bool(lower)), out.ctypes.data,
+                                             counts.ctypes.data)
+    return rc, out, counts[:S]
+
+
+def online_cpus() -> int:
+    return int(_load().oracle_online_cpus())

@@ -55,9 +55,11 @@
  * points in general position, and against closed forms and invariants.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 typedef __int128 i128;
 
@@ -241,3 +243,185 @@ int oracle_orient_signs(const float *a, const float *b, const float *c,
   }
   return OR_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * All-cores variants, for the CPU baseline's timing only.
+ *
+ * The same chain, split over threads, relying on one fact of the hood's
+ * definition: a point that is no corner of the hood of a subset holding it
+ * (it lies on or below a segment between two points of the subset, or below
+ * a point of the subset at its x) is no corner of the hood of the whole set
+ * either.  So the hood of a set cut into x-ordered chunks is the hood of the
+ * union of the chunks' hoods.  Chunk cuts are moved forward to the start of
+ * a run of equal x, so every run lies in one chunk and its representative is
+ * chosen exactly as in the single chain.  Each thread validates, converts
+ * and chains one chunk; one final chain over the concatenated chunk hoods
+ * (still in x order) gives the result.  Data errors are reported for the
+ * lowest failing index, with the checks of one point taken in the order of
+ * the single-threaded `convert`.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  const float *xy;
+  int64_t lo, hi;     /* the chunk's points [lo, hi) */
+  int64_t *X, *Y;     /* whole-set buffers; this job fills [lo, hi) */
+  int32_t *hood_idx;  /* the chunk's hood, chunk-relative, at hood_idx + lo */
+  int64_t count;
+  int64_t err_pos;    /* lowest failing index in the chunk, -1 if none */
+  int err;
+  int lower;
+} chunk_job;
+
+static void *chunk_main(void *arg) {
+  chunk_job *j = (chunk_job *)arg;
+  j->err = OR_OK;
+  j->err_pos = -1;
+  j->count = 0;
+  for (int64_t i = j->lo; i < j->hi; ++i) {
+    int rc = grid_int(j->xy[2 * i], 0.0, 1.0, &j->X[i]);
+    if (!rc) rc = grid_int(j->xy[2 * i + 1], -1.0, 1.0, &j->Y[i]);
+    if (!rc && i > 0) {
+      int64_t prev = 0;
+      if (i > j->lo)
+        prev = j->X[i - 1];
+      else if (grid_int(j->xy[2 * i - 2], 0.0, 1.0, &prev))
+        prev = INT64_MIN; /* the previous chunk reports that point's error */
+      if (j->X[i] < prev) rc = OR_ERR_UNSORTED;
+    }
+    if (rc) {
+      j->err = rc;
+      j->err_pos = i;
+      return NULL;
+    }
+  }
+  if (j->lower)
+    for (int64_t i = j->lo; i < j->hi; ++i) j->Y[i] = -j->Y[i];
+  j->count = chain(j->X + j->lo, j->Y + j->lo, j->hi - j->lo, j->hood_idx + j->lo);
+  return NULL;
+}
+
+static int hood_mt(const float *xy, int64_t n, int32_t nthreads, int32_t *out_idx,
+                   int64_t *out_count, int lower) {
+  if (n < 0 || n > INT32_MAX || (n > 0 && (!xy || !out_idx)) || !out_count || nthreads < 1 ||
+      nthreads > 1024)
+    return OR_ERR_ARG;
+  *out_count = 0;
+  if (n == 0) return OR_OK;
+  int64_t T = nthreads;
+  if (T > n) T = n;
+  int64_t *X = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  int64_t *Y = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+  int32_t *hidx = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  chunk_job *jobs = (chunk_job *)calloc((size_t)T, sizeof(chunk_job));
+  pthread_t *tid = (pthread_t *)calloc((size_t)T, sizeof(pthread_t));
+  int rc = OR_OK;
+  if (!X || !Y || !hidx || !jobs || !tid) rc = OR_ERR_ARG;
+  if (rc == OR_OK) {
+    /* cuts: nominal k n / T, moved forward past a run of equal x */
+    int64_t lo = 0;
+    for (int64_t k = 0; k < T; ++k) {
+      int64_t hi = k + 1 == T ? n : (k + 1) * n / T;
+      if (hi < lo) hi = lo;
+      while (hi < n && hi > 0 && xy[2 * hi] == xy[2 * hi - 2]) ++hi;
+      jobs[k] = (chunk_job){xy, lo, hi, X, Y, hidx, 0, -1, OR_OK, lower};
+      lo = hi;
+    }
+    int64_t started = 0;
+    for (int64_t k = 1; k < T; ++k) {
+      if (pthread_create(&tid[k], NULL, chunk_main, &jobs[k]) != 0) break;
+      started = k;
+    }
+    chunk_main(&jobs[0]);
+    for (int64_t k = started + 1; k < T; ++k) chunk_main(&jobs[k]); /* not started */
+    for (int64_t k = 1; k <= started; ++k) pthread_join(tid[k], NULL);
+    for (int64_t k = 0; k < T; ++k)
+      if (jobs[k].err) { /* the lowest failing index is in the earliest failing chunk */
+        rc = jobs[k].err;
+        break;
+      }
+  }
+  if (rc == OR_OK) {
+    /* the final chain over the chunk hoods, in x order */
+    int64_t m = 0;
+    for (int64_t k = 0; k < T; ++k)
+      for (int64_t e = 0; e < jobs[k].count; ++e) {
+        const int64_t g = jobs[k].lo + hidx[jobs[k].lo + e];
+        X[m] = X[g];
+        Y[m] = Y[g];
+        out_idx[m] = (int32_t)g; /* candidate m's input index */
+        ++m;
+      }
+    int32_t *pos = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    if (!pos) {
+      rc = OR_ERR_ARG;
+    } else {
+      const int64_t h = chain(X, Y, m, pos);
+      for (int64_t e = 0; e < h; ++e) pos[e] = out_idx[pos[e]];
+      memcpy(out_idx, pos, (size_t)h * sizeof(int32_t));
+      *out_count = h;
+      free(pos);
+    }
+  }
+  free(X);
+  free(Y);
+  free(hidx);
+  free(jobs);
+  free(tid);
+  return rc;
+}
+
+/* Upper hood (lower = 0) or lower hood (lower = 1) of xy[0..n) on nthreads
+ * threads (1 .. 1024); the same result and status as oracle_upper_hull /
+ * oracle_lower_hull. */
+int oracle_hood_mt(const float *xy, int64_t n, int32_t nthreads, int32_t lower,
+                   int32_t *out_idx, int64_t *out_count) {
+  return hood_mt(xy, n, nthreads, out_idx, out_count, lower != 0);
+}
+
+typedef struct {
+  const float *xy;
+  const int64_t *offsets;
+  int64_t num_sets;
+  int32_t *out_idx;
+  int64_t *out_counts;
+  int lower;
+  int64_t next; /* next set to take (atomic) */
+} sets_job;
+
+static void *sets_main(void *arg) {
+  sets_job *j = (sets_job *)arg;
+  for (;;) {
+    const int64_t s = __atomic_fetch_add(&j->next, 1, __ATOMIC_RELAXED);
+    if (s >= j->num_sets) return NULL;
+    const int64_t lo = j->offsets[s], hi = j->offsets[s + 1];
+    int64_t cnt = 0;
+    const int rc = hood(j->xy + 2 * lo, hi - lo, j->out_idx + lo, &cnt, j->lower);
+    j->out_counts[s] = rc ? rc : cnt;
+  }
+}
+
+/* Many sets on nthreads threads, each set's chain on one thread (sets taken
+ * in index order as threads become free); the same layout and per-set
+ * statuses as oracle_upper_hull_batched / oracle_lower_hull_batched.
+ * Returns 0 or the status of the lowest-numbered failing set. */
+int oracle_hood_batched_mt(const float *xy, const int64_t *offsets, int64_t num_sets,
+                           int32_t nthreads, int32_t lower, int32_t *out_idx,
+                           int64_t *out_counts) {
+  if (num_sets < 0 || !offsets || (num_sets > 0 && !out_counts) || nthreads < 1 ||
+      nthreads > 1024)
+    return OR_ERR_ARG;
+  sets_job job = {xy, offsets, num_sets, out_idx, out_counts, lower != 0, 0};
+  pthread_t tid[1024];
+  int32_t started = 0;
+  for (int32_t k = 1; k < nthreads; ++k) {
+    if (pthread_create(&tid[k], NULL, sets_main, &job) != 0) break;
+    started = k;
+  }
+  sets_main(&job);
+  for (int32_t k = 1; k <= started; ++k) pthread_join(tid[k], NULL);
+  for (int64_t s = 0; s < num_sets; ++s)
+    if (out_counts[s] < 0) return (int)out_counts[s];
+  return OR_OK;
+}
+
+/* Threads available to this process (the CPU baseline reports it). */
+int32_t oracle_online_cpus(void) { return (int32_t)sysconf(_SC_NPROCESSORS_ONLN); }
