@@ -183,6 +183,13 @@ def main():
     ap.add_argument("--unsorted", action="store_true",
                     help="shuffle every set (seeded) and let the library sort it by x on the "
                          "device first")
+    ap.add_argument("--no-elimination", action="store_true",
+                    help="UH_FLAG_NO_ELIMINATION: every point goes through the serial strip "
+                         "hoods and every round of Wagener merges (the method itself, no "
+                         "filter in front)")
+    ap.add_argument("--check-signs", action="store_true",
+                    help="UH_FLAG_CHECK_SIGNS: every orientation test also in 128-bit integers "
+                         "(soundness check; slow)")
     ap.add_argument("--flush", action="store_true",
                     help="cold caches: overwrite a 1 GiB buffer before every timed step (outside "
                          "the step's own events), so the input is read from HBM, not the 256 MB "
@@ -233,7 +240,9 @@ def main():
     flags = (uh.UH_FLAG_GRAPH if args.graph else 0) | \
         (uh.UH_FLAG_FORCE_FALLBACK if args.force_fallback else 0) | \
         (uh.UH_FLAG_BOTH_HOODS if args.both_hoods else 0) | \
-        (uh.UH_FLAG_UNSORTED if args.unsorted else 0)
+        (uh.UH_FLAG_UNSORTED if args.unsorted else 0) | \
+        (uh.UH_FLAG_NO_ELIMINATION if args.no_elimination else 0) | \
+        (uh.UH_FLAG_CHECK_SIGNS if args.check_signs else 0)
     H = 2 if args.both_hoods else 1  # hoods per set
     fan_in = 0
     tuned = None
@@ -248,7 +257,7 @@ def main():
     plan_cfg = plan.config
     out_idx = torch.empty(max(H * N, 1), dtype=torch.int32, device=dev)
     out_cnt = torch.empty(H * S, dtype=torch.int32, device=dev)
-    stats = torch.zeros((H * S, 2), dtype=torch.int64, device=dev)
+    stats = uh.new_stats(H * S, dev)
 
     ev = HipEvents()
     probes = []
@@ -261,8 +270,9 @@ def main():
     cnt_np = out_cnt.cpu().numpy()
     if np.any(cnt_np < 0):
         sys.exit(f"bench: data error status {cnt_np.min()}")
-    st = stats.cpu().numpy()
-    evals, fallbacks = int(st[:, 0].sum()), int(st[:, 1].sum())
+    st = uh.decode_stats(stats.cpu().numpy())
+    evals, fallbacks = int(st["orient_evals"].sum()), int(st["fallbacks"].sum())
+    sign_errors = int(st["sign_errors"].sum()) if args.check_signs else None
 
     for _ in range(args.warmup):
         plan.run(pts, out_idx, out_cnt)
@@ -363,7 +373,7 @@ def main():
     roofline = None
     if tile_ms:
         achieved = alg_tile / (tile_ms * 1e-3) / 1e9
-        traffic = None if (args.both_hoods or args.unsorted) else \
+        traffic = None if (args.both_hoods or args.unsorted or args.no_elimination) else \
             load_traffic(args.workload, args.strip)
         roofline = {"bound": "hbm", "kernel": "tile_kernel", "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -419,6 +429,8 @@ def main():
                    "corners": h_total,
                    "orient_evals_per_point": round(evals / max(N, 1), 3),
                    "fallback_rate": (fallbacks / evals) if evals else 0.0,
+                   "elimination": not args.no_elimination,
+                   "sign_errors": sign_errors,
                    "path_hbm_frac": round(path_gbs / HBM_PEAK_GBS, 4),
                    "matches_oracle": checked},
         "roofline": roofline,

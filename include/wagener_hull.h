@@ -60,8 +60,12 @@ extern "C" {
 #define UH_ERR_ARG (-1)       /* NULL pointer, negative size, bad config   */
 #define UH_ERR_ALLOC (-2)     /* device allocation failed                  */
 #define UH_ERR_HIP (-3)       /* a HIP runtime call failed                 */
-#define UH_ERR_CAPTURE (-4)   /* a plan would have to be built while the   */
-                              /* stream is being captured into a graph     */
+#define UH_ERR_CAPTURE (-4)   /* device memory would have to be allocated  */
+                              /* while the stream is being captured into a */
+                              /* graph                                      */
+#define UH_ERR_WORKSPACE (-5) /* the workspace set with                    */
+                              /* upper_hull_set_workspace is too small for */
+                              /* this call                                  */
 #define UH_ERR_UNSORTED (-10) /* data: x decreases somewhere               */
 #define UH_ERR_RANGE (-11)    /* data: x outside [0,1], y outside [-1,1],  */
                               /*       or a NaN / infinity                 */
@@ -71,11 +75,22 @@ extern "C" {
 /* Human-readable text of a status code (static storage, never NULL). */
 const char *upper_hull_status_string(int status);
 
-/* Per-set counters written by the batched entry point (device memory). */
+/* Per-set counters written by the batched entry points (device memory). */
 typedef struct {
   uint64_t orient_evals; /* orientation tests evaluated                    */
   uint64_t fallbacks;    /* of which the FP32 filter could not decide and  */
                          /* the exact FP64 evaluation was used             */
+  uint64_t sign_errors;  /* with UH_FLAG_CHECK_SIGNS: tests whose sign     */
+                         /* differed from a 128-bit integer evaluation     */
+                         /* (0 on data that meets the contract)            */
+  int32_t rounds;        /* rounds of pairwise merges over the set's       */
+                         /* serial strip hoods of `strip` points:          */
+                         /* ceil(log2(ceil(n / strip))), 0 for n <= strip; */
+                         /* the strips stand for the paper's first         */
+                         /* log2(strip) - 1 stages, which start at blocks  */
+                         /* of two points                                  */
+  int32_t status;        /* 0, or the set's negative data-error status     */
+                         /* (the same value as its count)                  */
 } upper_hull_stats;
 
 /* Plan options.  A NULL config pointer means the defaults. */
@@ -105,6 +120,43 @@ typedef struct {
                                   /* input indices, left to right.  At most */
                                   /* 2^32 - 1 points; adds about 36 bytes   */
                                   /* per point of workspace.                */
+#define UH_FLAG_NO_ELIMINATION 32u /* no elimination of points before the   */
+                                  /* merges: every point goes through the   */
+                                  /* serial strip hoods and every round of  */
+                                  /* Wagener merges (same result; for       */
+                                  /* measuring the method itself and for    */
+                                  /* upper_hull_plan_trace)                 */
+#define UH_FLAG_CHECK_SIGNS 64u   /* soundness check: every orientation    */
+                                  /* test is also evaluated in 128-bit      */
+                                  /* integers; disagreements are counted in */
+                                  /* upper_hull_stats.sign_errors (slow)    */
+
+/* -------------------------------------------------------------- workspace */
+/*
+ * Device memory for the single-set calls (upper_hull and convex_hull).
+ * Without a workspace set, the library keeps one per (device, stream),
+ * allocated on first use and enlarged when a call needs more (allocation is
+ * refused while the stream is capturing: UH_ERR_CAPTURE).  With a workspace
+ * set, those calls allocate nothing, never synchronise the device and can be
+ * captured into a graph for any size that fits.
+ *
+ * upper_hull_workspace_bytes: bytes that serve every call with at most
+ * max_total_n points over at most max_sets sets (max_total_n >= 0,
+ * max_sets >= 1): upper_hull of n points is one set of n points; convex_hull
+ * of n points is two sets of n points (its upper and lower hood), so it needs
+ * max_total_n >= 2 n and max_sets >= 2.  About 12 bytes per point plus small
+ * tables.  Returns 0 for invalid arguments.
+ *
+ * upper_hull_set_workspace: from now on the single-set calls on the current
+ * device use device_ptr[0 .. bytes) (256-byte aligned, caller-owned, not
+ * freed by the library); a call it cannot serve returns UH_ERR_WORKSPACE and
+ * enqueues nothing.  device_ptr = NULL, bytes = 0 goes back to library
+ * memory.  Calls that use one workspace must not overlap in time (calls on
+ * one stream never do); its contents between calls are the library's.
+ * Synchronous; not while a stream of the device is capturing.
+ */
+size_t upper_hull_workspace_bytes(int64_t max_total_n, int32_t max_sets);
+int upper_hull_set_workspace(void *device_ptr, size_t bytes);
 
 /* ------------------------------------------------------------ single set */
 /*
@@ -116,12 +168,10 @@ typedef struct {
  *   out_count device int32[1]: the corner count, or a negative data-error
  *             status.
  *   stream    HIP stream the work is enqueued on.
- * The library keeps a plan (schedule + workspace of about 12 bytes per
- * point) per distinct n, built on first use; building one is not allowed
- * while `stream` is capturing (UH_ERR_CAPTURE): call once before capture.
- * This is the paper's whole program (its stage loop and match_and_merge
- * launches) as one device-resident call.  Calls for the same n share that
- * plan's workspace, so calls on different streams must not overlap.
+ * The schedule follows from n (no table, nothing uploaded); the working
+ * memory comes from the workspace (see upper_hull_set_workspace).  This is
+ * the paper's whole program (its stage loop and match_and_merge launches) as
+ * one device-resident call of two or three kernel launches.
  */
 int upper_hull(const float *points, int64_t n, int32_t *out_idx,
                int32_t *out_count, hipStream_t stream);
@@ -138,9 +188,8 @@ int upper_hull(const float *points, int64_t n, int32_t *out_idx,
  *   out_idx    device int32[n]: every index appears at most once.
  *   out_count  device int32[1]: the corner count, or a negative data-error
  *              status (the same checks as upper_hull).
- * Keeps its own cached plan per n (workspace about 24 bytes per point plus
- * 8 bytes per point of hood buffers); the same rules as upper_hull apply
- * (no plan building during capture, no overlapping calls for one n).
+ * Uses the workspace as upper_hull does, with two sets of n points (about
+ * 28 bytes per point), plus one launch that joins the two hoods.
  */
 int convex_hull(const float *points, int64_t n, int32_t *out_idx,
                 int32_t *out_count, hipStream_t stream);
@@ -214,12 +263,43 @@ void upper_hull_plan_destroy(upper_hull_plan *plan);
 int upper_hull_plan_sorted(const upper_hull_plan *plan, const float **sorted_points,
                            const int32_t **perm);
 
+/*
+ * The blocks of one level of a plan's merge tree (level 0: the tiles of
+ * 64 * strip points; level k >= 1: the blocks formed by merge pass k, each
+ * the union of up to fan_in blocks of level k - 1 of one set; the last level
+ * holds one block per set that needed that many passes).  Returns the number
+ * of blocks (or UH_ERR_ARG for a level outside 0 .. number of passes); with
+ * ranges != NULL (HOST int64[2 * blocks]) also block b's first point and
+ * point count, in the plan's point numbering (with UH_FLAG_BOTH_HOODS the
+ * lower hood of input point i is point set_offsets[num_sets] + i).
+ */
+int32_t upper_hull_plan_blocks(const upper_hull_plan *plan, int32_t level, int64_t *ranges);
+
+/*
+ * Debug trace of the merge tree, the paper's per-stage dump of every block's
+ * hood: runs the plan's tile pass and its first `level` merge passes on
+ * `points` (the whole run for the last level), then writes for every block b
+ * of that level its corners' set-relative indices, left to right, at
+ * out_idx + (block b's first point) and its count to out_counts[b].  With
+ * UH_FLAG_NO_ELIMINATION every block then holds exactly the upper hood of its
+ * points; otherwise blocks hold what survived the elimination, and a count
+ * with bit 31 set marks a tile's sorted surviving points rather than a hood.
+ *   out_idx     device int32[plan points] (both hoods: twice the points).
+ *   out_counts  device int32[upper_hull_plan_blocks(plan, level, NULL)].
+ * Not for UH_FLAG_UNSORTED plans.  Allocates a small buffer on first use.
+ * Leaves the plan ready for normal runs.
+ */
+int upper_hull_plan_trace(upper_hull_plan *plan, const float *points, int32_t level,
+                          int32_t *out_idx, int32_t *out_counts, hipStream_t stream);
+
 /* The configuration a plan was built with, defaults resolved (strip,
  * fan_in, flags) into *config. */
 int upper_hull_plan_config(const upper_hull_plan *plan, upper_hull_config *config);
 
-/* Number of kernel launches one run of the plan enqueues (for profiling). */
-int upper_hull_plan_launches(const upper_hull_plan *plan);
+/* Number of kernel launches one run of the plan enqueues (for profiling);
+ * with_stats != 0: a run given a stats array (which adds the clearing
+ * launch when no set is empty). */
+int upper_hull_plan_launches(const upper_hull_plan *plan, int32_t with_stats);
 
 /*
  * Profiling hook: later runs of the plan record `before` on the run's

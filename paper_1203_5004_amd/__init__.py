@@ -26,6 +26,7 @@ UH_ERR_ARG = -1
 UH_ERR_ALLOC = -2
 UH_ERR_HIP = -3
 UH_ERR_CAPTURE = -4
+UH_ERR_WORKSPACE = -5
 UH_ERR_UNSORTED = -10
 UH_ERR_RANGE = -11
 UH_ERR_GRID = -12
@@ -35,12 +36,16 @@ UH_FLAG_NO_VALIDATE = 2
 UH_FLAG_GRAPH = 4
 UH_FLAG_BOTH_HOODS = 8
 UH_FLAG_UNSORTED = 16
+UH_FLAG_NO_ELIMINATION = 32
+UH_FLAG_CHECK_SIGNS = 64
 
 EXPORTS = (
     "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_batched",
+    "upper_hull_workspace_bytes", "upper_hull_set_workspace",
     "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
     "upper_hull_plan_set_probe", "upper_hull_plan_sorted", "upper_hull_plan_config",
+    "upper_hull_plan_blocks", "upper_hull_plan_trace",
     "upper_hull_autotune",
     "upper_hull_read_reference",
     "upper_hull_bridge", "upper_hull_orient",
@@ -48,7 +53,28 @@ EXPORTS = (
 
 
 class upper_hull_stats(ctypes.Structure):
-    _fields_ = [("orient_evals", ctypes.c_uint64), ("fallbacks", ctypes.c_uint64)]
+    _fields_ = [("orient_evals", ctypes.c_uint64), ("fallbacks", ctypes.c_uint64),
+                ("sign_errors", ctypes.c_uint64),
+                ("rounds", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+# one upper_hull_stats record = STATS_WORDS int64 words of a torch tensor
+STATS_WORDS = ctypes.sizeof(upper_hull_stats) // 8
+
+
+def new_stats(num, device="cuda"):
+    """A zeroed device tensor holding `num` upper_hull_stats records."""
+    torch = _torch()
+    return torch.zeros((num, STATS_WORDS), dtype=torch.int64, device=device)
+
+
+def decode_stats(words) -> dict:
+    """Fields of stats records copied to the host (int64 array [num, STATS_WORDS])."""
+    w = np.ascontiguousarray(np.asarray(words, dtype=np.int64).reshape(-1, STATS_WORDS))
+    rec = w.view(np.dtype([("orient_evals", "<u8"), ("fallbacks", "<u8"),
+                           ("sign_errors", "<u8"),
+                           ("rounds", "<i4"), ("status", "<i4")])).reshape(-1)
+    return {k: rec[k].copy() for k in rec.dtype.names}
 
 
 class upper_hull_config(ctypes.Structure):
@@ -84,7 +110,7 @@ def load_library():
     lib.upper_hull_plan_run.restype = ctypes.c_int
     lib.upper_hull_plan_destroy.argtypes = [p]
     lib.upper_hull_plan_destroy.restype = None
-    lib.upper_hull_plan_launches.argtypes = [p]
+    lib.upper_hull_plan_launches.argtypes = [p, i32]
     lib.upper_hull_plan_launches.restype = ctypes.c_int
     lib.upper_hull_plan_set_probe.argtypes = [p, p, p]
     lib.upper_hull_plan_set_probe.restype = ctypes.c_int
@@ -92,10 +118,18 @@ def load_library():
     lib.upper_hull_autotune.restype = ctypes.c_int
     lib.upper_hull_plan_config.argtypes = [p, p]
     lib.upper_hull_plan_config.restype = ctypes.c_int
+    lib.upper_hull_plan_blocks.argtypes = [p, i32, p]
+    lib.upper_hull_plan_blocks.restype = ctypes.c_int32
+    lib.upper_hull_plan_trace.argtypes = [p, p, i32, p, p, p]
+    lib.upper_hull_plan_trace.restype = ctypes.c_int
     lib.upper_hull_plan_sorted.argtypes = [p, ctypes.POINTER(p), ctypes.POINTER(p)]
     lib.upper_hull_plan_sorted.restype = ctypes.c_int
     lib.upper_hull_read_reference.argtypes = [p, i64, i32, p, p]
     lib.upper_hull_read_reference.restype = ctypes.c_int
+    lib.upper_hull_workspace_bytes.argtypes = [i64, i32]
+    lib.upper_hull_workspace_bytes.restype = ctypes.c_size_t
+    lib.upper_hull_set_workspace.argtypes = [p, ctypes.c_size_t]
+    lib.upper_hull_set_workspace.restype = ctypes.c_int
     lib.upper_hull_bridge.argtypes = [p, i32, p, i32, i32, p, p]
     lib.upper_hull_bridge.restype = ctypes.c_int
     lib.upper_hull_orient.argtypes = [p, p, p, i64, p, p, i32, p]
@@ -193,8 +227,8 @@ def upper_hull_batched(points, set_offsets, out_idx=None, out_counts=None, stats
         raise ValueError("output buffers too small")
     if stats is not None:
         _dev_tensor(stats, torch.int64, "stats")
-        if stats.numel() < 2 * S:
-            raise ValueError("stats needs 2 int64 per set")
+        if stats.numel() < STATS_WORDS * S:
+            raise ValueError(f"stats needs {STATS_WORDS} int64 per set (new_stats)")
     _check(load_library().upper_hull_batched(_ptr(points), off.ctypes.data, S, _ptr(out_idx),
                                              _ptr(out_counts), _ptr(stats), _stream(stream)))
     return out_idx, out_counts
@@ -227,7 +261,11 @@ class Plan:
 
     @property
     def launches(self) -> int:
-        return load_library().upper_hull_plan_launches(self._h)
+        """Kernel launches per run without stats."""
+        return load_library().upper_hull_plan_launches(self._h, 0)
+
+    def launches_with_stats(self) -> int:
+        return load_library().upper_hull_plan_launches(self._h, 1)
 
     def set_probe(self, before, after):
         """Record raw hipEvent_t handles (ints) around the tile kernel."""
@@ -251,6 +289,45 @@ class Plan:
             assert hip.hipMemcpy(ctypes.c_void_p(perm.ctypes.data), pm, ctypes.c_size_t(4 * n), d2h) == 0
         return xy, perm
 
+    @property
+    def passes(self) -> int:
+        """Merge passes of a run (levels of the merge tree above the tiles)."""
+        k = 0
+        while load_library().upper_hull_plan_blocks(self._h, k + 1, None) >= 0:
+            k += 1
+        return k
+
+    def blocks(self, level: int) -> np.ndarray:
+        """(first point, point count) of every block of a merge-tree level."""
+        lib = load_library()
+        nb = lib.upper_hull_plan_blocks(self._h, level, None)
+        _check(min(nb, 0))
+        r = np.zeros((max(nb, 1), 2), dtype=np.int64)
+        _check(min(lib.upper_hull_plan_blocks(self._h, level, r.ctypes.data), 0))
+        return r[:nb]
+
+    def trace(self, points, level: int, stream=None):
+        """Run up to a merge-tree level and return, on the host, every block's
+        (count, corner indices relative to its set); see upper_hull_plan_trace."""
+        torch = _torch()
+        _dev_tensor(points, torch.float32, "points")
+        rng = self.blocks(level)
+        out = torch.full((max(self.hoods * self.total, 1),), -7, dtype=torch.int32,
+                         device=points.device)
+        cnt = torch.full((max(len(rng), 1),), -7, dtype=torch.int32, device=points.device)
+        _check(load_library().upper_hull_plan_trace(self._h, _ptr(points), level, _ptr(out),
+                                                    _ptr(cnt), _stream(stream)))
+        torch.cuda.synchronize()
+        o, c = out.cpu().numpy(), cnt.cpu().numpy()
+        res = []
+        for b, (s, _) in enumerate(rng):
+            raw = int(c[b])
+            if -1000 < raw < 0:  # a data-error status
+                res.append((raw, None))
+            else:
+                res.append((raw, o[s:s + (raw & 0x7fffffff)].copy()))
+        return res
+
     def run(self, points, out_idx, out_counts, stats=None, stream=None):
         torch = _torch()
         _dev_tensor(points, torch.float32, "points")
@@ -262,8 +339,8 @@ class Plan:
             raise ValueError("out_counts too small")
         if stats is not None:
             _dev_tensor(stats, torch.int64, "stats")
-            if stats.numel() < 2 * self.hoods * self.num_sets:
-                raise ValueError("stats needs 2 int64 per set and hood")
+            if stats.numel() < STATS_WORDS * self.hoods * self.num_sets:
+                raise ValueError("stats needs one record per set and hood (new_stats)")
         _check(load_library().upper_hull_plan_run(
             self._h, _ptr(points), _ptr(out_idx), _ptr(out_counts), _ptr(stats),
             _stream(stream)))
@@ -308,6 +385,26 @@ def upper_hull_read_reference(points, reps=20, stream=None):
     _check(load_library().upper_hull_read_reference(_ptr(points), points.numel() // 2, reps,
                                                     ctypes.byref(ms), _stream(stream)))
     return ms.value
+
+
+def upper_hull_workspace_bytes(max_total_n: int, max_sets: int = 1) -> int:
+    """Bytes of a workspace that serves every single-set call with at most
+    max_total_n points over max_sets sets (convex_hull of n points: 2 n points
+    over 2 sets)."""
+    return int(load_library().upper_hull_workspace_bytes(int(max_total_n), int(max_sets)))
+
+
+def upper_hull_set_workspace(buffer):
+    """Let the single-set calls on the buffer's device use `buffer` (a CUDA
+    uint8 tensor, 256-byte aligned; keep it alive while it is set), or go back
+    to library memory with None.  Returns the buffer."""
+    torch = _torch()
+    if buffer is None:
+        _check(load_library().upper_hull_set_workspace(ctypes.c_void_p(0), 0))
+        return None
+    _dev_tensor(buffer, torch.uint8, "buffer")
+    _check(load_library().upper_hull_set_workspace(_ptr(buffer), buffer.numel()))
+    return buffer
 
 
 def upper_hull_bridge(P, Q, lanes=64, stream=None):

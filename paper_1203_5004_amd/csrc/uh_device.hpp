@@ -17,11 +17,32 @@ namespace uh {
 
 enum : int { LOW = -1, EQUAL = 0, HIGH = 1 };
 
-// Per-lane counters of orientation tests and exact fallbacks.
+// Per-lane counters of orientation tests and exact fallbacks; with `check`
+// every sign is also compared with a 128-bit integer evaluation and
+// disagreements are counted (the predicate's soundness check).
 struct OrientCount {
   uint32_t evals = 0;
   uint32_t fallbacks = 0;
+  uint32_t sign_errors = 0;
+  bool check = false;
 };
+
+// Sign of det(q - p, r - p) in 128-bit integers: every coordinate on the
+// 2^-30 grid is an integer multiple of 2^-30 (scaling by 2^30 and converting
+// is exact), so the determinant of the integer coordinates has the exact
+// sign.  Used only by the soundness check.
+__device__ __noinline__ int orient_int128(float px, float py, float qx, float qy, float rx,
+                                          float ry) {
+  const long long X0 = (long long)((double)px * 1073741824.0);
+  const long long Y0 = (long long)((double)py * 1073741824.0);
+  const long long X1 = (long long)((double)qx * 1073741824.0);
+  const long long Y1 = (long long)((double)qy * 1073741824.0);
+  const long long X2 = (long long)((double)rx * 1073741824.0);
+  const long long Y2 = (long long)((double)ry * 1073741824.0);
+  const __int128 d = (__int128)(X1 - X0) * (__int128)(Y2 - Y0) -
+                     (__int128)(Y1 - Y0) * (__int128)(X2 - X0);
+  return (d > 0) - (d < 0);
+}
 
 // Exact sign of det(q - p, r - p) for coordinates on the 2^-30 grid with
 // x in [0, 1] and y in [-1, 1].
@@ -73,10 +94,15 @@ __device__ __forceinline__ int orient_sign(float px, float py, float qx,
   const float r = dy1 * dx2;
   const float det = l - r;
   const float bound = (__builtin_fabsf(l) + __builtin_fabsf(r)) * 0x1p-22f;
-  if (!force_exact && (__builtin_fabsf(det) > bound || bound == 0.0f))
-    return (det > 0.0f) - (det < 0.0f);
-  cnt.fallbacks++;
-  return orient_exact(px, py, qx, qy, rx, ry);
+  int sg;
+  if (!force_exact && (__builtin_fabsf(det) > bound || bound == 0.0f)) {
+    sg = (det > 0.0f) - (det < 0.0f);
+  } else {
+    cnt.fallbacks++;
+    sg = orient_exact(px, py, qx, qy, rx, ry);
+  }
+  if (cnt.check && sg != orient_int128(px, py, qx, qy, rx, ry)) cnt.sign_errors++;
+  return sg;
 }
 
 __device__ __forceinline__ int orient_sign(float2 p, float2 q, float2 r,

@@ -89,6 +89,18 @@ struct MergeItem {   // one workgroup of a merge pass
   int32_t pad;
 };
 
+// A merge pass of a single-set run (both hoods: two mirrored sets of the
+// same size): its items follow from their index, so no table is read.
+struct PassArgs {
+  int64_t stride;    // child k of an item starts at off + k * stride
+  int32_t children;  // blocks of the previous level per set
+  int32_t fan;       // children per item (the last item takes the rest)
+  int32_t items;     // items per set in this pass
+  int32_t level;     // as MergeItem::level
+  int32_t groups;    // first-level items per set
+  int32_t pad;
+};
+
 struct RunArgs {
   const float2 *pts;
   const int64_t *set_start;  // [S + 1]
@@ -117,8 +129,7 @@ struct RunArgs {
 __device__ __forceinline__ int check_point(float2 v) {
   // data contract: x in [0,1], y in [-1,1] (NaN fails both), both on the
   // 2^-30 grid: scaling by 2^30 is exact, and then no fraction may remain
-  if (!(__builtin_fabsf(v.x - 0.5f) <= 0.5f && __builtin_fabsf(v.y) <= 1.0f))
-    return UH_ERR_RANGE;
+  if (!(v.x >= 0.0f && v.x <= 1.0f && __builtin_fabsf(v.y) <= 1.0f)) return UH_ERR_RANGE;
   const float fr = __builtin_amdgcn_fractf(v.x * 0x1p30f) + __builtin_amdgcn_fractf(v.y * 0x1p30f);
   return fr == 0.0f ? 0 : UH_ERR_GRID;
 }
@@ -126,22 +137,6 @@ __device__ __forceinline__ int check_point(float2 v) {
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-// Adds the workgroup's orientation counters to stats[set] (if any).
-__device__ __forceinline__ void flush_stats(const RunArgs &A, int set,
-                                            const OrientCount &oc,
-                                            unsigned long long *sstat) {
-  const uint32_t e = wave_sum(oc.evals), f = wave_sum(oc.fallbacks);
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&sstat[0], (unsigned long long)e);
-    atomicAdd(&sstat[1], (unsigned long long)f);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && A.stats) {
-    atomicAdd((unsigned long long *)&A.stats[set].orient_evals, sstat[0]);
-    atomicAdd((unsigned long long *)&A.stats[set].fallbacks, sstat[1]);
-  }
 }
 
 // Equal-x rule at the junction of two hoods (vertical closure): if P's last
@@ -157,16 +152,51 @@ __device__ __forceinline__ void junction_rule(float2 plast, float2 qfirst,
   }
 }
 
+// Start of set s's points (and of its output slots).  A single-set run
+// (both hoods: set 1 is the mirrored copy, its slots n further on) needs no
+// table.
+__device__ __forceinline__ int64_t set_base(const RunArgs &A, int s) {
+  return A.one_set ? (int64_t)s * A.n_points : A.set_start[s];
+}
+__device__ __forceinline__ int64_t set_size(const RunArgs &A, int s) {
+  return A.one_set ? A.n_points : A.set_start[s + 1] - A.set_start[s];
+}
+
+// Rounds of pairwise merges over a set's serial strip hoods of K points:
+// ceil(log2(ceil(n / K))) (the strips themselves stand for the paper's first
+// log2(K) - 1 stages, which start at blocks of two points).
+__device__ __forceinline__ int32_t merge_rounds(int64_t n, int K) {
+  const int64_t strips = (n + K - 1) / K;
+  int32_t r = 0;
+  while (((int64_t)1 << r) < strips) ++r;
+  return r;
+}
+
+// The set's final writer records its status and round count in the stats.
+__device__ __forceinline__ void finish_stats(const RunArgs &A, int set, int32_t status) {
+  if (A.stats) {
+    A.stats[set].rounds = merge_rounds(set_size(A, set), A.tile_len / 64);
+    A.stats[set].status = status;
+  }
+}
+
 // ---------------------------------------------------------------- init
-__global__ void init_kernel(int32_t S, RunArgs A) {
+// Also clears the first `groups` group maxima: a run in a workspace shared
+// by runs of other shapes cannot rely on the previous run having left them
+// zero (a plan's own workspace can: every run's final merges zero them).
+__global__ void init_kernel(int32_t S, int32_t groups, RunArgs A) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < groups) A.group_max[(int64_t)s * GROUP_STRIDE] = 0u;
   if (s >= S) return;
   A.set_status[s] = 0;
   if (A.stats) {
     A.stats[s].orient_evals = 0;
     A.stats[s].fallbacks = 0;
+    A.stats[s].sign_errors = 0;
+    A.stats[s].rounds = 0;
+    A.stats[s].status = 0;
   }
-  if (A.set_start[s + 1] == A.set_start[s]) A.out_counts[s] = 0;
+  if (set_size(A, s) == 0) A.out_counts[s] = 0;
 }
 
 // ---------------------------------------------------------------- tiles
@@ -264,11 +294,20 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 __device__ __forceinline__ void flush_wave_stats(const RunArgs &A, int set, OrientCount &oc) {
   if (!A.stats) return;
   const uint32_t e = wave_sum(oc.evals), f = wave_sum(oc.fallbacks);
+  const uint32_t x = wave_sum(oc.sign_errors);
   if ((threadIdx.x & 63) == 0 && A.stats && e) {
     atomicAdd((unsigned long long *)&A.stats[set].orient_evals, (unsigned long long)e);
     atomicAdd((unsigned long long *)&A.stats[set].fallbacks, (unsigned long long)f);
+    if (x) atomicAdd((unsigned long long *)&A.stats[set].sign_errors, (unsigned long long)x);
   }
-  oc.evals = oc.fallbacks = 0;
+  oc.evals = oc.fallbacks = oc.sign_errors = 0;
+}
+
+// The counters of a kernel of this run (soundness check on request).
+__device__ __forceinline__ OrientCount run_counter(const RunArgs &A) {
+  OrientCount oc;
+  oc.check = (A.flags & UH_FLAG_CHECK_SIGNS) != 0;
+  return oc;
 }
 
 // Order-preserving unsigned code of a float (larger float, larger code;
@@ -347,7 +386,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
   const bool fin = it.rel0 == 0 && it.len == it.set_len;  // the set's only tile
   float2 *st = sxy + lane * S;
   uint16_t *sl = sid + lane * S;
-  OrientCount oc;
+  OrientCount oc = run_counter(A);
   float ymax = TILE_PAD_Y;
 #pragma unroll
   for (int i = 0; i < K; ++i) ymax = fmaxf(ymax, p[i].y);
@@ -365,7 +404,10 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
   const int rel0 = it.rel0;
 
   // ---- 3. elimination; few survivors leave as a point list
-  if ((K == 16 || K == 32) && !fin) {
+  // Without elimination (UH_FLAG_NO_ELIMINATION) every point of the tile
+  // goes through the strip hoods and the rounds, and the tile leaves a hood.
+  const bool noelim = (A.flags & UH_FLAG_NO_ELIMINATION) != 0;
+  if ((K == 16 || K == 32) && !fin && !noelim) {
     constexpr int SPP = 64 / K;  // candidate strips per pass
     const uint64_t cand = __ballot(ymax > exp_pre || ymax >= exp_suf);
     const int ncand = __builtin_popcountll(cand);
@@ -427,7 +469,10 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     }
   }
   uint32_t keep = 0;
-  {
+  if (noelim) {
+    const int my_len = min(max(it.len - lane * K, 0), K);
+    keep = my_len >= 32 ? ~0u : (1u << my_len) - 1u;
+  } else {
     float bm = exp_pre;  // max y over earlier points of the set
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -445,7 +490,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
   // the first point of its strip lies, and the tile runs the exact test if
   // 48 lanes find theirs below (not on the noise of a nearly straight run).
   bool chord_ran = false;
-  {
+  if (!noelim) {
     const int ll = it.len - 1, lane_l = ll / K, il = ll % K;
     const float2 tf = make_float2(readlane(p[0].x, 0), readlane(p[0].y, 0));
     const float2 tl = sxy[lane_l * S + 2 * ((il >> 1) ^ tile_swz<K>(lane_l)) + (il & 1)];
@@ -464,7 +509,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
       }
     }
   }
-  if ((K != 16 && K != 32) || chord_ran) {
+  if (((K != 16 && K != 32) || chord_ran) && !noelim) {
     // few survivors leave as a sorted point list: ranks by a wave prefix sum
     // (with strips of 16 or 32 the height test's survivors were counted
     // already; only the chord tests can have left few)
@@ -537,7 +582,10 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     if (__ballot(err != 0)) err = wave_min(err);
     int32_t *dst = A.out_idx + (it.start - it.rel0);
     for (int k = lane; k < hc; k += 64) dst[k] = rel0 + (int)sid[hb + k];
-    if (lane == 0) A.out_counts[it.set] = err ? err : hc;
+    if (lane == 0) {
+      A.out_counts[it.set] = err ? err : hc;
+      finish_stats(A, it.set, err);
+    }
   } else {
     for (int k = lane; k < hc; k += 64) {
       A.ws_xy[it.start + k] = sxy[hb + k];
@@ -890,6 +938,26 @@ struct Rope {
   }
 };
 
+// Merge item b of a pass: from the table, or in a single-set run from the
+// pass's shape (item i of set v).
+__device__ __forceinline__ MergeItem merge_item(const RunArgs &A, const MergeItem *items,
+                                                const PassArgs &pa, int b) {
+  if (!A.one_set) return items[b];
+  MergeItem it;
+  const int v = b / pa.items, i = b - v * pa.items;
+  it.child0 = v * pa.children + i * pa.fan;
+  it.nch = min(pa.fan, pa.children - i * pa.fan);
+  it.off = (int64_t)v * A.n_points + (int64_t)i * pa.fan * pa.stride;
+  it.stride = pa.stride;
+  it.set = v;
+  it.final_ = pa.items == 1;
+  it.g0 = v * pa.groups;
+  it.ng = pa.groups;
+  it.level = pa.level;
+  it.pad = 0;
+  return it;
+}
+
 // One workgroup of BLK threads merges the hoods of up to BLK consecutive
 // blocks of the previous level of one set (log2 BLK more rounds).  When their corners fit
 // in LDS: gather them back to back, six rounds inside each wave (64
@@ -898,7 +966,8 @@ struct Rope {
 // of lanes, narrowing per-child intervals instead of moving corners.
 template <int BLK, int VMX>
 __global__ __launch_bounds__(BLK) void merge_kernel(
-    RunArgs A, const MergeItem *items, const int32_t *child_cnt, int32_t *cnt_out) {
+    RunArgs A, const MergeItem *items, PassArgs pa, const int32_t *child_cnt,
+    int32_t *cnt_out) {
   // VMX corners (x, y, index) for the LDS path; the global path reuses the
   // same bytes as 1.5 * VMX corner positions (x, y)
   __shared__ __attribute__((aligned(16))) char lds_corners[VMX * 12];
@@ -912,10 +981,11 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   __shared__ int swave[BLK / 64 + 1];
   __shared__ float4 sw4[BLK / 64];
 
-  const MergeItem it = items[blockIdx.x];
+  const MergeItem it = merge_item(A, items, pa, (int)blockIdx.x);
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
+  const bool noelim = (A.flags & UH_FLAG_NO_ELIMINATION) != 0;
   const int nch = it.nch;
 
   // A child is a hood, or (POINTS_FLAG) a tile's sorted surviving points.
@@ -953,7 +1023,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       }
     }
     block_excl_max<BLK>(cm, gp, gs, wpre, wsuf, sw4);
-    cand = cm > wpre || cm >= wsuf;
+    cand = noelim || cm > wpre || cm >= wsuf;
   } else {
     const int64_t last = A.n_total - 1;
 #pragma unroll
@@ -975,7 +1045,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   soff[tid] = o;
   int npow = 1;
   while (npow < nch) npow <<= 1;
-  OrientCount oc;
+  OrientCount oc = run_counter(A);
   __syncthreads();
 
   if (V <= VMX) {
@@ -1043,7 +1113,9 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         block_excl_max<BLK>(cmax, -2.0f, -2.0f, pre, suf, sw4);
       }
       int kept = 0;
-      if (__syncthreads_or(c > 256)) {
+      if (noelim) {
+        kept = c;  // every gathered corner stays
+      } else if (__syncthreads_or(c > 256)) {
         // Some child is large (an arc's steep end tiles, where nearly every
         // point is a corner): the filter is shared by all threads, thread t
         // taking entries [t * J, t * J + J) of the V gathered ones.  An entry
@@ -1218,12 +1290,13 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       }
       const int hb = sblk[0].x, hc = sblk[0].y;
       if (it.final_) {
-        int32_t *dst = A.out_idx + A.set_start[it.set];
+        int32_t *dst = A.out_idx + set_base(A, it.set);
         for (int k = lane; k < hc; k += 64) dst[k] = bid[hb + k];
         if (lane == 0) {
           const int st = A.set_status[it.set];
           A.out_counts[it.set] = st ? st : hc;
           if (st) A.set_status[it.set] = 0;  // zero again for the next run
+          finish_stats(A, it.set, st);
         }
       } else {
         for (int k = lane; k < hc; k += 64) {
@@ -1332,7 +1405,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   const int hc = cum[BLK];
   const Rope R{A.ws_xy, cum, klo, it.off, it.stride, 0, nch, 0};  // reads the workspace
   if (it.final_) {
-    int32_t *dst = A.out_idx + A.set_start[it.set];
+    int32_t *dst = A.out_idx + set_base(A, it.set);
     for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {
       int32_t vi[8];
 #pragma unroll
@@ -1350,6 +1423,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       const int st = A.set_status[it.set];
       A.out_counts[it.set] = st ? st : hc;
       if (st) A.set_status[it.set] = 0;  // zero again for the next run
+      finish_stats(A, it.set, st);
     }
   } else {
     // compact to the item's slot: corner e comes from at or after slot
@@ -1428,6 +1502,51 @@ __global__ void unsort_kernel(const int64_t *set_start, int32_t in_sets, const i
   }
 }
 
+// Debug trace of one level of the merge tree (the paper's per-stage dump of
+// every block's hood): block b of `level` (0: the tiles, k: the items of
+// merge pass k) writes its corners' set-relative indices at out_idx + its
+// first point and its count (bit 31: a tile's sorted surviving points rather
+// than a hood) to out_counts[b].  A block that finished its set wrote both to
+// the run's outputs already (A.out_idx, A.out_counts), where they are read.
+__global__ void trace_kernel(RunArgs A, int32_t level, int32_t tiles_per_set,
+                             const TileItem *tiles, const MergeItem *items, PassArgs pa,
+                             const int32_t *cnt, int32_t *out_counts) {
+  const int b = blockIdx.x;
+  int64_t start;
+  int set;
+  bool fin;
+  if (level == 0) {
+    if (A.one_set) {
+      const int v = b / tiles_per_set, t = b - v * tiles_per_set;
+      start = (int64_t)v * A.n_points + (int64_t)t * A.tile_len;
+      set = v;
+      fin = tiles_per_set == 1;
+    } else {
+      const TileItem it = tiles[b];
+      start = it.start;
+      set = it.set;
+      fin = it.rel0 == 0 && it.len == it.set_len;
+    }
+  } else {
+    const MergeItem it = merge_item(A, items, pa, b);
+    start = it.off;
+    set = it.set;
+    fin = it.final_ != 0;
+  }
+  const int32_t c = fin ? A.out_counts[set] : cnt[b];
+  if (!fin) {
+    const int32_t m = (int32_t)((uint32_t)c & ~POINTS_FLAG);
+    for (int k = threadIdx.x; k < m; k += blockDim.x) A.out_idx[start + k] = A.ws_idx[start + k];
+  }
+  if (threadIdx.x == 0) out_counts[b] = c;
+}
+
+// Writes `value` to out[0 .. m) (counts of empty single-set runs).
+__global__ void fill_kernel(int32_t *out, int32_t m, int32_t value) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m) out[t] = value;
+}
+
 // ---------------------------------------------------------------- probes
 __global__ void bridge_kernel(const float2 *P, int hp, const float2 *Q, int hq,
                               int L, int32_t *out_ab) {
@@ -1455,44 +1574,151 @@ __global__ void orient_kernel(const float2 *a, const float2 *b, const float2 *c,
 // ====================================================================== host
 using namespace uh;
 
-struct upper_hull_plan {
-  int device = 0;
-  int32_t S = 0;
-  int64_t N = 0;
-  int K = 16, T = 4096, F = 256;
-  uint32_t flags = 0;
-  bool both = false;       // upper and lower hood: S, N, ntiles, ngroups count both
-  int32_t in_S = 0;        // input sets
-  int64_t in_N = 0;        // input points
-  int32_t ntiles = 0;
-  bool has_empty = false;  // some set has no points
-  int32_t ngroups = 0;     // first-level merge items
-  int32_t group_fan = 1;   // single set: tiles per group
-  uint32_t *tile_max = nullptr, *group_max = nullptr;
-  std::vector<int32_t> pass_items;  // merge items per pass
-  std::vector<char> pass_wide;      // per pass: some item has more than BLOCK children
-  // device memory
-  int64_t *d_set_start = nullptr;
-  TileItem *d_tiles = nullptr;
-  int32_t *d_cnt0 = nullptr;
-  std::vector<MergeItem *> d_items;
-  std::vector<int32_t *> d_cnt;   // per pass: item corner counts
-  float2 *ws_xy = nullptr;
-  int32_t *ws_idx = nullptr;
-  int32_t *set_status = nullptr;
-  // graph cache: (points, out_idx, out_counts, stats) -> exec
-  std::map<std::tuple<const void *, void *, void *, void *>, hipGraphExec_t> graphs;
-  hipStream_t cap_stream = nullptr;
-  hipEvent_t probe_before = nullptr, probe_after = nullptr;
-  int32_t *hull_idx = nullptr, *hull_cnt = nullptr;  // convex_hull: both hoods before joining
-  bool unsorted = false;            // sort every set by x first (UH_FLAG_UNSORTED)
-  uh_rs::RadixPlan rs;
-  float2 *sorted = nullptr;         // [in_N] the points in sorted order
-  int32_t *perm = nullptr;          // [in_N] their set-relative input indices
-  std::mutex mu;
-};
+struct upper_hull_plan;
 
 namespace {
+
+constexpr int MAX_PASSES = 40;
+
+// Merge passes of a single set of n points (with both hoods, two mirrored
+// sets of n points): the shape of every pass follows from n, K and F.
+struct SingleShape {
+  int64_t n = 0;
+  bool both = false;
+  int K = 16, T = 1024, F = 256;
+  int32_t VS = 1;         // sets: 1, or 2 with both hoods
+  int32_t tiles = 0;      // per set
+  int32_t groups = 0;     // first-level merge items per set
+  int32_t group_fan = 1;  // tiles per first-level item
+  int npass = 0;
+  PassArgs pass[MAX_PASSES];
+  bool wide[MAX_PASSES];
+};
+
+// Everything one run enqueues.
+struct Launch {
+  RunArgs A;
+  int32_t S = 0;             // sets (with both hoods: both halves)
+  int32_t tile_grid = 0;     // tile kernel workgroups (with both hoods: the upper half)
+  int K = 16;
+  bool both = false;
+  const TileItem *tiles = nullptr;
+  int32_t *cnt0 = nullptr;
+  int npass = 0;
+  int32_t pass_items[MAX_PASSES];
+  bool pass_wide[MAX_PASSES];
+  const MergeItem *items[MAX_PASSES];
+  int32_t *cnt[MAX_PASSES];
+  PassArgs pa[MAX_PASSES];
+  bool init = false;         // launch init_kernel first
+  int32_t init_groups = 0;   // group maxima it clears
+  hipEvent_t probe_before = nullptr, probe_after = nullptr;
+};
+
+int cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return cus;
+}
+
+// Default fan-in: 256; for a plan of at least 8 tiles per compute unit (a
+// "large" plan), the largest of 256, 128, 64 that still gives the first merge
+// pass an item per compute unit.  A large set in few, large items would leave
+// most units idle while each item runs its rounds; a small plan keeps the
+// fewest passes.
+int default_fan_in(const int64_t *off, int32_t S, int T, int cus, bool *large) {
+  int64_t all_tiles = 0;
+  for (int32_t s = 0; s < S; ++s) all_tiles += (off[s + 1] - off[s] + T - 1) / T;
+  *large = all_tiles >= 8 * (int64_t)cus;
+  int F = BLOCK;
+  auto first_items = [&](int f) {
+    int64_t items = 0;
+    for (int32_t s = 0; s < S; ++s) {
+      const int64_t nt = (off[s + 1] - off[s] + T - 1) / T;
+      if (nt > 1) items += (nt + f - 1) / f;
+    }
+    return items;
+  };
+  if (*large)
+    while (F > 64 && first_items(F) < cus) F >>= 1;
+  return F;
+}
+
+// The passes of a single-set run, by the rules of upper_hull_plan_create.
+void single_shape(int64_t n, bool both, int K, int F, bool large, SingleShape &sh) {
+  sh.n = n;
+  sh.both = both;
+  sh.K = K;
+  sh.T = 64 * K;
+  sh.F = F;
+  sh.VS = both ? 2 : 1;
+  sh.tiles = (int32_t)((n + sh.T - 1) / sh.T);
+  sh.npass = 0;
+  sh.groups = 0;
+  sh.group_fan = F;
+  int64_t stride = sh.T;
+  int32_t count = sh.tiles;
+  while (count > 1 && sh.npass < MAX_PASSES) {
+    // a set with BLOCK + 1 .. WIDE blocks left finishes in one wide workgroup
+    const bool use_wide = F == BLOCK && count > BLOCK && count <= WIDE;
+    const int32_t FS = use_wide ? WIDE : F;
+    const int32_t items = (count + FS - 1) / FS;
+    PassArgs &pa = sh.pass[sh.npass];
+    pa.stride = stride;
+    pa.children = count;
+    pa.fan = FS;
+    pa.items = items;
+    pa.level = std::min(sh.npass, 2);
+    pa.pad = 0;
+    // the wide workgroup for more than BLOCK children, and in a large plan
+    // for a pass of few items, whose merges are large and latency-bound
+    sh.wide[sh.npass] = (large && (int64_t)items * sh.VS <= 64) || FS > BLOCK;
+    if (sh.npass == 0) {
+      sh.groups = items;
+      sh.group_fan = FS;
+    }
+    ++sh.npass;
+    count = items;
+    stride *= F;
+  }
+  for (int k = 0; k < sh.npass; ++k) sh.pass[k].groups = sh.groups;
+}
+
+// Byte layout of a single-set run's working memory (256-byte aligned parts).
+struct SingleLayout {
+  size_t status = 0, group_max = 0, tile_max = 0, cnt0 = 0, ws_idx = 0, ws_xy = 0;
+  size_t hull_idx = 0, hull_cnt = 0, total = 0;
+  size_t cnt[MAX_PASSES];
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+SingleLayout single_layout(const SingleShape &sh, bool hull_buffers) {
+  SingleLayout L;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t here = at;
+    at += align256(std::max<size_t>(bytes, 4));
+    return here;
+  };
+  const size_t VS = (size_t)sh.VS, N = VS * (size_t)sh.n;
+  L.status = take(4 * VS);
+  L.group_max = take(4 * GROUP_STRIDE * VS * (size_t)sh.groups);
+  L.tile_max = take(4 * VS * (size_t)sh.tiles);
+  L.cnt0 = take(4 * VS * (size_t)sh.tiles);
+  for (int k = 0; k < sh.npass; ++k) L.cnt[k] = take(4 * VS * (size_t)sh.pass[k].items);
+  L.ws_idx = take(4 * N);
+  L.ws_xy = take(8 * N);
+  if (hull_buffers) {
+    L.hull_idx = take(4 * N);
+    L.hull_cnt = take(4 * VS);
+  }
+  L.total = at;
+  return L;
+}
 
 template <class T>
 int dalloc(T **p, size_t count) {
@@ -1510,48 +1736,26 @@ int upload(T *dst, const std::vector<T> &src) {
              : UH_ERR_HIP;
 }
 
-void free_plan_memory(upper_hull_plan *p) {
-  (void)hipFree(p->d_set_start);
-  (void)hipFree(p->d_tiles);
-  (void)hipFree(p->d_cnt0);
-  for (auto *q : p->d_items) (void)hipFree(q);
-  for (auto *q : p->d_cnt) (void)hipFree(q);
-  (void)hipFree(p->ws_xy);
-  (void)hipFree(p->ws_idx);
-  (void)hipFree(p->set_status);
-  (void)hipFree(p->tile_max);
-  (void)hipFree(p->group_max);
-  (void)hipFree(p->hull_idx);
-  (void)hipFree(p->hull_cnt);
-  uh_rs::radix_plan_free(&p->rs);
-  (void)hipFree(p->sorted);
-  (void)hipFree(p->perm);
-  for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+int capturing(hipStream_t stream, bool *yes) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
+  *yes = cs != hipStreamCaptureStatusNone;
+  return UH_OK;
 }
 
-int enqueue_run(upper_hull_plan *p, const RunArgs &A0, hipStream_t stream) {
-  RunArgs A = A0;
-  if (p->unsorted) {  // the sort by x in front: the hull reads the sorted copy
-    const int rc = uh_rs::radix_sort_enqueue(p->rs, A0.pts, p->in_N, p->sorted, p->perm, stream);
-    if (rc) return rc;
-    A.pts = p->sorted;
+int enqueue(const Launch &L, hipStream_t stream) {
+  const RunArgs &A = L.A;
+  if (L.init) {
+    const int m = std::max(L.S, L.init_groups);
+    hipLaunchKernelGGL(init_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, L.S,
+                       L.init_groups, A);
   }
-  // Per-set status starts at zero (plan creation) and the final merge of a
-  // set that saw an error zeroes it again, so the clearing pass is needed
-  // only for stats counters and for empty sets' counts.
-  if (A.stats || p->has_empty) {
-    const int nb = (p->S + 255) / 256;
-    hipLaunchKernelGGL(init_kernel, dim3(nb), dim3(256), 0, stream, p->S, A);
-  }
-  if (p->ntiles > 0) {
-    // with both hoods, one wave per input tile computes both of its hoods
-    const dim3 grid(p->both ? p->ntiles / 2 : p->ntiles), blk(64);
-    if (p->probe_before && hipEventRecord(p->probe_before, stream) != hipSuccess)
-      return UH_ERR_HIP;
+  if (L.tile_grid > 0) {
+    const dim3 grid(L.tile_grid), blk(64);
+    if (L.probe_before && hipEventRecord(L.probe_before, stream) != hipSuccess) return UH_ERR_HIP;
 #define UH_TILE(KK, BB) \
-  hipLaunchKernelGGL((tile_kernel<KK, BB>), grid, blk, 0, stream, A, p->d_tiles, p->d_cnt0)
-    switch (p->K * 2 + (p->both ? 1 : 0)) {
+  hipLaunchKernelGGL((tile_kernel<KK, BB>), grid, blk, 0, stream, A, L.tiles, L.cnt0)
+    switch (L.K * 2 + (L.both ? 1 : 0)) {
       case 8: UH_TILE(4, false); break;
       case 9: UH_TILE(4, true); break;
       case 16: UH_TILE(8, false); break;
@@ -1563,61 +1767,271 @@ int enqueue_run(upper_hull_plan *p, const RunArgs &A0, hipStream_t stream) {
       default: return UH_ERR_ARG;
     }
 #undef UH_TILE
-    if (p->probe_after && hipEventRecord(p->probe_after, stream) != hipSuccess)
-      return UH_ERR_HIP;
+    if (L.probe_after && hipEventRecord(L.probe_after, stream) != hipSuccess) return UH_ERR_HIP;
   }
-  for (size_t ps = 0; ps < p->pass_items.size(); ++ps) {
-    const int32_t *ccnt = ps == 0 ? p->d_cnt0 : p->d_cnt[ps - 1];
-    if (p->pass_wide[ps])
-      hipLaunchKernelGGL((merge_kernel<WIDE, VMAX_WIDE>), dim3(p->pass_items[ps]), dim3(WIDE), 0,
-                         stream, A, p->d_items[ps], ccnt, p->d_cnt[ps]);
+  for (int ps = 0; ps < L.npass; ++ps) {
+    const int32_t *ccnt = ps == 0 ? L.cnt0 : L.cnt[ps - 1];
+    if (L.pass_wide[ps])
+      hipLaunchKernelGGL((merge_kernel<WIDE, VMAX_WIDE>), dim3(L.pass_items[ps]), dim3(WIDE), 0,
+                         stream, A, L.items[ps], L.pa[ps], ccnt, L.cnt[ps]);
     else
-      hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), dim3(p->pass_items[ps]), dim3(BLOCK), 0,
-                         stream, A, p->d_items[ps], ccnt, p->d_cnt[ps]);
+      hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), dim3(L.pass_items[ps]), dim3(BLOCK), 0,
+                         stream, A, L.items[ps], L.pa[ps], ccnt, L.cnt[ps]);
   }
+  return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+}  // namespace
+
+struct upper_hull_plan {
+  int device = 0;
+  int32_t S = 0;
+  int64_t N = 0;
+  int K = 16, T = 4096, F = 256;
+  uint32_t flags = 0;
+  bool both = false;       // upper and lower hood: S, N, ntiles, ngroups count both
+  int32_t in_S = 0;        // input sets
+  int64_t in_N = 0;        // input points
+  int32_t ntiles = 0;
+  bool has_empty = false;  // some set has no points
+  int32_t ngroups = 0;     // first-level merge items
+  int32_t group_fan = 1;   // single set: tiles per first-level item
+  SingleShape single;      // a plan of one input set: its passes follow from n
+  std::vector<int64_t> h_voff;               // set starts (both halves)
+  std::vector<TileItem> h_tiles;             // host copies of the tables (more
+  std::vector<std::vector<MergeItem>> h_items;  // than one set), for the trace
+  int32_t *trace_cnt = nullptr;              // run counts of upper_hull_plan_trace
+  uint32_t *tile_max = nullptr, *group_max = nullptr;
+  std::vector<int32_t> pass_items;  // merge items per pass
+  std::vector<char> pass_wide;      // per pass: the wide merge workgroup
+  // device memory
+  int64_t *d_set_start = nullptr;
+  TileItem *d_tiles = nullptr;
+  int32_t *d_cnt0 = nullptr;
+  std::vector<MergeItem *> d_items;
+  std::vector<int32_t *> d_cnt;   // per pass: item corner counts
+  float2 *ws_xy = nullptr;
+  int32_t *ws_idx = nullptr;
+  int32_t *set_status = nullptr;
+  // graph cache: (points, out_idx, out_counts, stats) -> exec, least recently
+  // used first; at most GRAPH_CACHE entries
+  static constexpr size_t GRAPH_CACHE = 8;
+  std::vector<std::pair<std::tuple<const void *, void *, void *, void *>, hipGraphExec_t>> graphs;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t probe_before = nullptr, probe_after = nullptr;
+  bool unsorted = false;            // sort every set by x first (UH_FLAG_UNSORTED)
+  uh_rs::RadixPlan rs;
+  float2 *sorted = nullptr;         // [in_N] the points in sorted order
+  int32_t *perm = nullptr;          // [in_N] their set-relative input indices
+  std::mutex mu;
+};
+
+namespace {
+
+void free_plan_memory(upper_hull_plan *p) {
+  (void)hipFree(p->d_set_start);
+  (void)hipFree(p->d_tiles);
+  (void)hipFree(p->d_cnt0);
+  for (auto *q : p->d_items) (void)hipFree(q);
+  for (auto *q : p->d_cnt) (void)hipFree(q);
+  (void)hipFree(p->ws_xy);
+  (void)hipFree(p->ws_idx);
+  (void)hipFree(p->set_status);
+  (void)hipFree(p->tile_max);
+  (void)hipFree(p->group_max);
+  uh_rs::radix_plan_free(&p->rs);
+  (void)hipFree(p->sorted);
+  (void)hipFree(p->perm);
+  (void)hipFree(p->trace_cnt);
+  for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+}
+
+Launch plan_launch(upper_hull_plan *p, const RunArgs &A, bool with_stats) {
+  Launch L;
+  L.A = A;
+  L.S = p->S;
+  L.tile_grid = p->both ? p->ntiles / 2 : p->ntiles;  // one wave per input tile does both hoods
+  L.K = p->K;
+  L.both = p->both;
+  L.tiles = p->d_tiles;
+  L.cnt0 = p->d_cnt0;
+  L.npass = (int)p->pass_items.size();
+  for (int k = 0; k < L.npass; ++k) {
+    L.pass_items[k] = p->pass_items[k];
+    L.pass_wide[k] = p->pass_wide[k] != 0;
+    L.items[k] = p->d_items.empty() ? nullptr : p->d_items[k];
+    L.cnt[k] = p->d_cnt[k];
+    L.pa[k] = p->in_S == 1 ? p->single.pass[k] : PassArgs{};
+  }
+  // Per-set status starts at zero (plan creation) and the final merge of a
+  // set that saw an error zeroes it again, so the clearing pass is needed
+  // only for stats counters and for empty sets' counts.
+  L.init = with_stats || p->has_empty;
+  L.init_groups = 0;
+  L.probe_before = p->probe_before;
+  L.probe_after = p->probe_after;
+  return L;
+}
+
+int enqueue_run(upper_hull_plan *p, const RunArgs &A0, hipStream_t stream) {
+  RunArgs A = A0;
+  if (p->unsorted) {  // the sort by x in front: the hull reads the sorted copy
+    const int rc = uh_rs::radix_sort_enqueue(p->rs, A0.pts, p->in_N, p->sorted, p->perm, stream);
+    if (rc) return rc;
+    A.pts = p->sorted;
+  }
+  int rc = enqueue(plan_launch(p, A, A.stats != nullptr), stream);
+  if (rc) return rc;
   if (p->unsorted)
     hipLaunchKernelGGL(unsort_kernel, dim3(p->S), dim3(256), 0, stream, p->d_set_start, p->in_S,
                        p->perm, A.out_idx, A.out_counts);
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
 
-std::mutex g_cache_mu;
-std::map<std::tuple<int, int64_t, uint32_t>, upper_hull_plan *> g_single_plans;
-// batched calls without a plan: one cached plan per (device, set layout)
-std::map<std::pair<int, std::vector<int64_t>>, upper_hull_plan *> g_batched_plans;
+// ---- workspaces of the single-set calls
+struct Workspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<int, Workspace> g_user_ws;                           // device -> caller's workspace
+std::map<std::pair<int, hipStream_t>, Workspace> g_lib_ws;    // (device, stream) -> library's
 
-// The cached single-set plan for n points on the current device (flags:
-// UH_FLAG_BOTH_HOODS for the convex hull, which also gets its buffers).
-int single_plan(int64_t n, uint32_t flags, hipStream_t stream, upper_hull_plan **out) {
+// The workspace a single-set call on `stream` uses, at least `need` bytes.
+int single_workspace(size_t need, hipStream_t stream, void **out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
-  std::lock_guard<std::mutex> lock(g_cache_mu);
-  auto key = std::make_tuple(dev, n, flags);
-  auto it = g_single_plans.find(key);
-  if (it != g_single_plans.end()) {
-    *out = it->second;
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  auto u = g_user_ws.find(dev);
+  if (u != g_user_ws.end()) {
+    if (u->second.bytes < need) return UH_ERR_WORKSPACE;
+    *out = u->second.ptr;
     return UH_OK;
   }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
-  if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
-  if (g_single_plans.size() >= 8) {  // bounded cache: drop the oldest
-    upper_hull_plan_destroy(g_single_plans.begin()->second);
-    g_single_plans.erase(g_single_plans.begin());
+  Workspace &w = g_lib_ws[std::make_pair(dev, stream)];
+  if (w.bytes < need) {
+    bool cap = false;
+    int rc = capturing(stream, &cap);
+    if (rc) return rc;
+    if (cap) return UH_ERR_CAPTURE;
+    // work already enqueued on this stream may still use the old memory:
+    // hipFree waits for it
+    if (w.ptr) (void)hipFree(w.ptr);
+    w.ptr = nullptr;
+    w.bytes = 0;
+    const size_t want = std::max(need, (size_t)(1 << 20));
+    if (hipMalloc(&w.ptr, want) != hipSuccess) {
+      w.ptr = nullptr;
+      return UH_ERR_ALLOC;
+    }
+    w.bytes = want;
   }
-  const int64_t off[2] = {0, n};
-  const upper_hull_config cfg = {0, 0, flags};
-  upper_hull_plan *p = nullptr;
-  int rc = upper_hull_plan_create(off, 1, &cfg, &p);
-  if (!rc && (flags & UH_FLAG_BOTH_HOODS)) {
-    rc = dalloc(&p->hull_idx, (size_t)(2 * n));
-    rc = rc ? rc : dalloc(&p->hull_cnt, 2);
-    if (rc) upper_hull_plan_destroy(p);
-  }
-  if (rc) return rc;
-  g_single_plans.emplace(key, p);
-  *out = p;
+  *out = w.ptr;
   return UH_OK;
+}
+
+// One set of n points (with both hoods: its upper hood into out_idx[0 .. n),
+// out_count[0], and its lower hood into out_idx[n .. 2n), out_count[1]; the
+// hood buffers inside the workspace if hood_bufs is given).
+int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int32_t *out_count,
+               hipStream_t stream, int32_t **hood_idx, int32_t **hood_cnt) {
+  const int K = 16;
+  bool large = false;
+  const int64_t off[2] = {0, n};
+  const int F = default_fan_in(off, 1, 64 * K, cu_count(), &large);
+  SingleShape sh;
+  single_shape(n, both, K, F, large, sh);
+  const bool bufs = hood_idx != nullptr;
+  const SingleLayout L = single_layout(sh, bufs);
+  void *base = nullptr;
+  int rc = single_workspace(L.total, stream, &base);
+  if (rc) return rc;
+  char *b = static_cast<char *>(base);
+  if (bufs) {
+    *hood_idx = reinterpret_cast<int32_t *>(b + L.hull_idx);
+    *hood_cnt = reinterpret_cast<int32_t *>(b + L.hull_cnt);
+    out_idx = *hood_idx;
+    out_count = *hood_cnt;
+  }
+  if (n == 0) {
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(64), 0, stream, out_count, sh.VS, 0);
+    return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
+  }
+  Launch La;
+  RunArgs &A = La.A;
+  A.pts = reinterpret_cast<const float2 *>(points);
+  A.set_start = nullptr;
+  A.ws_xy = reinterpret_cast<float2 *>(b + L.ws_xy);
+  A.ws_idx = reinterpret_cast<int32_t *>(b + L.ws_idx);
+  A.set_status = reinterpret_cast<int32_t *>(b + L.status);
+  A.out_idx = out_idx;
+  A.out_counts = out_count;
+  A.stats = nullptr;
+  A.n_total = (int64_t)sh.VS * n;
+  A.tile_len = sh.T;
+  A.one_set = 1;
+  A.group_fan = sh.group_fan;
+  A.tile_max = reinterpret_cast<uint32_t *>(b + L.tile_max);
+  A.group_max = reinterpret_cast<uint32_t *>(b + L.group_max);
+  A.flags = both ? UH_FLAG_BOTH_HOODS : 0u;
+  A.n_points = n;
+  A.lower_n = both ? n : 0;
+  A.lower_tiles = both ? sh.tiles : 0;
+  A.lower_groups = both ? sh.groups : 0;
+  A.lower_sets = both ? 1 : 0;
+  La.S = sh.VS;
+  La.tile_grid = sh.tiles;
+  La.K = K;
+  La.both = both;
+  La.cnt0 = reinterpret_cast<int32_t *>(b + L.cnt0);
+  La.npass = sh.npass;
+  for (int k = 0; k < sh.npass; ++k) {
+    La.pass_items[k] = sh.VS * sh.pass[k].items;
+    La.pass_wide[k] = sh.wide[k];
+    La.items[k] = nullptr;
+    La.cnt[k] = reinterpret_cast<int32_t *>(b + L.cnt[k]);
+    La.pa[k] = sh.pass[k];
+  }
+  // the workspace may hold anything from runs of other shapes: clear the
+  // status and group maxima this run reads (a one-tile set reads neither)
+  La.init = sh.tiles > 1;
+  La.init_groups = sh.VS * sh.groups;
+  return enqueue(La, stream);
+}
+
+// ---- cached plans of the batched call without a plan object
+struct CachedPlan {
+  upper_hull_plan *plan = nullptr;
+  uint64_t last_use = 0;
+  int in_use = 0;               // calls between taking the plan and enqueueing
+  bool captured = false;        // used while a stream was capturing: never dropped
+  hipEvent_t done = nullptr;    // recorded after its latest run
+};
+constexpr size_t BATCHED_CACHE = 8;
+std::mutex g_cache_mu;
+uint64_t g_clock = 0;
+std::map<std::pair<int, std::vector<int64_t>>, CachedPlan> g_batched_plans;
+std::vector<CachedPlan> g_retired;  // dropped, freed once their last run is done
+
+// Frees retired plans whose last run has finished (never waits).
+void reap_retired() {
+  for (size_t k = 0; k < g_retired.size();) {
+    CachedPlan &c = g_retired[k];
+    if (!c.done || hipEventQuery(c.done) == hipSuccess) {
+      if (c.done) (void)hipEventDestroy(c.done);
+      upper_hull_plan *p = c.plan;
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      (void)hipSetDevice(p->device);
+      free_plan_memory(p);
+      (void)hipSetDevice(cur);
+      delete p;
+      g_retired.erase(g_retired.begin() + (long)k);
+    } else {
+      ++k;
+    }
+  }
 }
 
 }  // namespace
@@ -1630,12 +2044,46 @@ const char *upper_hull_status_string(int status) {
     case UH_ERR_ARG: return "invalid argument";
     case UH_ERR_ALLOC: return "device allocation failed";
     case UH_ERR_HIP: return "HIP runtime error";
-    case UH_ERR_CAPTURE: return "plan creation not allowed during stream capture";
+    case UH_ERR_CAPTURE: return "allocation needed while the stream is capturing";
+    case UH_ERR_WORKSPACE: return "the workspace set is too small for this call";
     case UH_ERR_UNSORTED: return "data error: x not non-decreasing";
     case UH_ERR_RANGE: return "data error: coordinate out of range or not finite";
     case UH_ERR_GRID: return "data error: coordinate not on the 2^-30 grid";
     default: return status >= 0 ? "ok (count)" : "unknown status";
   }
+}
+
+size_t upper_hull_workspace_bytes(int64_t max_total_n, int32_t max_sets) {
+  if (max_total_n < 0 || max_sets < 1 || max_total_n > ((int64_t)1 << 40)) return 0;
+  // A bound over every call that fits: tiles of T = 1024 points (each set
+  // adds at most one partial tile); first-level items of at least 64 tiles
+  // (or one per set); items of all later passes together at most the tiles;
+  // the parts' 256-byte alignment; and, for two sets or more, the hood
+  // buffers of convex_hull (4 bytes per point).
+  const size_t m = (size_t)max_total_n, s = (size_t)max_sets;
+  const size_t tiles = (m + 1023) / 1024 + s;
+  const size_t groups = tiles / 64 + 1 + s;
+  size_t b = 0;
+  b += align256(4 * s);                          // status
+  b += align256(4 * GROUP_STRIDE * groups);      // group maxima
+  b += 2 * align256(4 * tiles);                  // tile maxima, tile counts
+  b += align256(4 * tiles) + MAX_PASSES * 256;   // pass counts
+  b += align256(4 * m) + align256(8 * m);        // corner indices and positions
+  if (s >= 2) b += align256(4 * m) + align256(4 * s);  // hood buffers
+  return b;
+}
+
+int upper_hull_set_workspace(void *device_ptr, size_t bytes) {
+  if ((device_ptr == nullptr) != (bytes == 0)) return UH_ERR_ARG;
+  if (((uintptr_t)device_ptr & 255u) != 0) return UH_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  if (device_ptr)
+    g_user_ws[dev] = Workspace{device_ptr, bytes};
+  else
+    g_user_ws.erase(dev);
+  return UH_OK;
 }
 
 int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
@@ -1648,45 +2096,18 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
     if (set_offsets[s + 1] < set_offsets[s]) return UH_ERR_ARG;
     if (set_offsets[s + 1] - set_offsets[s] > INT32_MAX) return UH_ERR_ARG;
   }
-  int K = 16, F = 256;
+  int K = 16, F = 0;
   uint32_t flags = 0;
   if (config) {
     if (config->strip) K = config->strip;
-    if (config->fan_in) F = config->fan_in;
+    F = config->fan_in;
     flags = config->flags;
   }
   if (K != 4 && K != 8 && K != 16 && K != 32) return UH_ERR_ARG;
-  if (F < 2 || F > BLOCK || (F & (F - 1))) return UH_ERR_ARG;
-  // a large plan: at least 8 tiles per compute unit
-  int cus = 0;
-  {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-  }
-  int64_t all_tiles = 0;
-  for (int32_t s = 0; s < num_sets; ++s)
-    all_tiles += (set_offsets[s + 1] - set_offsets[s] + 64 * K - 1) / (64 * K);
-  const bool large_plan = all_tiles >= 8 * (int64_t)cus;
-  if (!(config && config->fan_in)) {
-    // Default fan-in: 256; for a plan of at least 8 tiles per compute unit,
-    // the largest of 256, 128, 64 that still gives the first merge pass an
-    // item per compute unit.  A large set in few, large items would leave
-    // most units idle while each item runs its rounds; a small plan keeps
-    // the fewest passes.
-    auto first_items = [&](int f) {
-      int64_t items = 0;
-      for (int32_t s = 0; s < num_sets; ++s) {
-        const int64_t nt = (set_offsets[s + 1] - set_offsets[s] + 64 * K - 1) / (64 * K);
-        if (nt > 1) items += (nt + f - 1) / f;
-      }
-      return items;
-    };
-    if (large_plan)
-      while (F > 64 && first_items(F) < cus) F >>= 1;
-  }
+  if (F != 0 && (F < 2 || F > BLOCK || (F & (F - 1)))) return UH_ERR_ARG;
+  bool large_plan = false;
+  const int Fdef = default_fan_in(set_offsets, num_sets, 64 * K, cu_count(), &large_plan);
+  if (F == 0) F = Fdef;
   // the sort's positions are 32-bit
   if ((flags & UH_FLAG_UNSORTED) && set_offsets[num_sets] > (int64_t)UINT32_MAX) return UH_ERR_ARG;
 
@@ -1710,132 +2131,150 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
   p->T = 64 * K;
   p->F = F;
   p->flags = flags;
-
-  // level 0: tiles; then merge passes of fan-in F until one hood per set
-  std::vector<TileItem> tiles;
-  std::vector<int32_t> first(VS), count(VS);  // blocks per set
-  for (int32_t s = 0; s < VS; ++s) {
-    const int64_t n = voff[s + 1] - voff[s];
-    const int64_t nt = (n + p->T - 1) / p->T;
-    first[s] = (int32_t)tiles.size();
-    count[s] = (int32_t)nt;
-    for (int64_t t = 0; t < nt; ++t) {
-      TileItem it;
-      it.start = voff[s] + t * p->T;
-      it.len = (int32_t)std::min<int64_t>(p->T, n - t * p->T);
-      it.set = s;
-      it.rel0 = (int32_t)(t * p->T);
-      it.nb_lo = (int16_t)std::min<int64_t>(16, t * p->T);
-      it.nb_hi = (int16_t)std::min<int64_t>(16, n - t * p->T - it.len);
-      it.set_len = (int32_t)n;
-      it.group = -1;  // set below, once the first merge level is known
-      tiles.push_back(it);
-    }
-  }
-  p->ntiles = (int32_t)tiles.size();
   for (int32_t s = 0; s < VS; ++s) p->has_empty = p->has_empty || voff[s + 1] == voff[s];
-  // Within a set the blocks of a level are consecutive and equally long
-  // (except the last), so child k of an item starts at off + k * stride.
-  std::vector<std::vector<MergeItem>> passes;
-  std::vector<int32_t> g0(VS, 0), ng(VS, 0), fs0(VS, F);  // first level per set
-  int64_t stride = p->T;
-  for (;;) {
-    std::vector<MergeItem> items;
-    std::vector<int32_t> nfirst(VS), ncount(VS);
-    // With the default fan-in, a set with BLOCK + 1 .. WIDE blocks left can
-    // finish in one wide workgroup (one per CU), if few sets need one.
-    int32_t nwide = 0;
-    for (int32_t s = 0; s < VS; ++s) nwide += F == BLOCK && count[s] > BLOCK && count[s] <= WIDE;
-    const bool use_wide = nwide > 0 && nwide <= 256;
-    for (int32_t s = 0; s < VS; ++s) {
-      nfirst[s] = (int32_t)items.size();
-      ncount[s] = 0;
-      if (count[s] <= 1) continue;
-      const int32_t FS = use_wide && F == BLOCK && count[s] <= WIDE ? WIDE : F;
-      const int32_t nitems = (count[s] + FS - 1) / FS;
-      for (int32_t i = 0; i < nitems; ++i) {
-        MergeItem m;
-        m.child0 = first[s] + i * FS;
-        m.nch = std::min(FS, count[s] - i * FS);
-        m.off = voff[s] + (int64_t)i * FS * stride;
-        m.stride = stride;
-        m.set = s;
-        m.final_ = nitems == 1;
-        m.level = std::min<int32_t>((int32_t)passes.size(), 2);
-        m.g0 = m.ng = m.pad = 0;
-        items.push_back(m);
-      }
-      ncount[s] = nitems;
-      if (passes.empty()) {
-        g0[s] = nfirst[s];
-        ng[s] = nitems;
-        fs0[s] = FS;
-      }
-    }
-    if (items.empty()) break;
-    passes.push_back(items);
-    stride *= F;
-    first = nfirst;
-    // sets finished in this pass keep count 1 -> no further items
-    for (int32_t s = 0; s < VS; ++s) count[s] = ncount[s];
-  }
 
-  // groups: the first-level items; every item knows its set's groups, and
-  // every tile of a set with more than one tile knows its group
-  for (auto &items : passes)
-    for (MergeItem &m : items) {
-      m.g0 = g0[m.set];
-      m.ng = ng[m.set];
+  std::vector<TileItem> tiles;
+  std::vector<std::vector<MergeItem>> passes;
+  if (num_sets == 1) {
+    // one set: every tile and merge item follows from its index
+    single_shape(p->in_N, both, K, F, large_plan, p->single);
+    const SingleShape &sh = p->single;
+    p->ntiles = sh.VS * sh.tiles;
+    p->ngroups = sh.VS * sh.groups;
+    p->group_fan = sh.group_fan;
+    for (int k = 0; k < sh.npass; ++k) {
+      p->pass_items.push_back(sh.VS * sh.pass[k].items);
+      p->pass_wide.push_back(sh.wide[k]);
     }
-  for (int32_t s = 0, t0 = 0; s < VS; ++s) {
-    const int64_t n = voff[s + 1] - voff[s];
-    const int32_t nt = (int32_t)((n + p->T - 1) / p->T);
-    if (nt > 1)
-      for (int32_t t = 0; t < nt; ++t) tiles[t0 + t].group = g0[s] + t / fs0[s];
-    t0 += nt;
+  } else {
+    // level 0: tiles; then merge passes of fan-in F until one hood per set
+    std::vector<int32_t> first(VS), count(VS);  // blocks per set
+    for (int32_t s = 0; s < VS; ++s) {
+      const int64_t n = voff[s + 1] - voff[s];
+      const int64_t nt = (n + p->T - 1) / p->T;
+      first[s] = (int32_t)tiles.size();
+      count[s] = (int32_t)nt;
+      for (int64_t t = 0; t < nt; ++t) {
+        TileItem it;
+        it.start = voff[s] + t * p->T;
+        it.len = (int32_t)std::min<int64_t>(p->T, n - t * p->T);
+        it.set = s;
+        it.rel0 = (int32_t)(t * p->T);
+        it.nb_lo = (int16_t)std::min<int64_t>(16, t * p->T);
+        it.nb_hi = (int16_t)std::min<int64_t>(16, n - t * p->T - it.len);
+        it.set_len = (int32_t)n;
+        it.group = -1;  // set below, once the first merge level is known
+        tiles.push_back(it);
+      }
+    }
+    p->ntiles = (int32_t)tiles.size();
+    // Within a set the blocks of a level are consecutive and equally long
+    // (except the last), so child k of an item starts at off + k * stride.
+    std::vector<int32_t> g0(VS, 0), ng(VS, 0), fs0(VS, F);  // first level per set
+    int64_t stride = p->T;
+    for (;;) {
+      std::vector<MergeItem> items;
+      std::vector<int32_t> nfirst(VS), ncount(VS);
+      // With the default fan-in, a set with BLOCK + 1 .. WIDE blocks left can
+      // finish in one wide workgroup (one per CU), if few sets need one.
+      int32_t nwide = 0;
+      for (int32_t s = 0; s < VS; ++s) nwide += F == BLOCK && count[s] > BLOCK && count[s] <= WIDE;
+      const bool use_wide = nwide > 0 && nwide <= 256;
+      for (int32_t s = 0; s < VS; ++s) {
+        nfirst[s] = (int32_t)items.size();
+        ncount[s] = 0;
+        if (count[s] <= 1) continue;
+        const int32_t FS = use_wide && F == BLOCK && count[s] <= WIDE ? WIDE : F;
+        const int32_t nitems = (count[s] + FS - 1) / FS;
+        for (int32_t i = 0; i < nitems; ++i) {
+          MergeItem m;
+          m.child0 = first[s] + i * FS;
+          m.nch = std::min(FS, count[s] - i * FS);
+          m.off = voff[s] + (int64_t)i * FS * stride;
+          m.stride = stride;
+          m.set = s;
+          m.final_ = nitems == 1;
+          m.level = std::min<int32_t>((int32_t)passes.size(), 2);
+          m.g0 = m.ng = m.pad = 0;
+          items.push_back(m);
+        }
+        ncount[s] = nitems;
+        if (passes.empty()) {
+          g0[s] = nfirst[s];
+          ng[s] = nitems;
+          fs0[s] = FS;
+        }
+      }
+      if (items.empty()) break;
+      passes.push_back(items);
+      stride *= F;
+      first = nfirst;
+      // sets finished in this pass keep count 1 -> no further items
+      for (int32_t s = 0; s < VS; ++s) count[s] = ncount[s];
+    }
+    // groups: the first-level items; every item knows its set's groups, and
+    // every tile of a set with more than one tile knows its group
+    for (auto &items : passes)
+      for (MergeItem &m : items) {
+        m.g0 = g0[m.set];
+        m.ng = ng[m.set];
+      }
+    for (int32_t s = 0, t0 = 0; s < VS; ++s) {
+      const int64_t n = voff[s + 1] - voff[s];
+      const int32_t nt = (int32_t)((n + p->T - 1) / p->T);
+      if (nt > 1)
+        for (int32_t t = 0; t < nt; ++t) tiles[t0 + t].group = g0[s] + t / fs0[s];
+      t0 += nt;
+    }
+    p->group_fan = fs0[0];
+    p->ngroups = passes.empty() ? 0 : (int32_t)passes[0].size();
+    if (both) {
+      // the tile kernel derives each lower tile from its upper twin: check that
+      // the schedule's second half is the first half moved by (N, S, tiles/2,
+      // groups/2), which holds because the two halves have the same set sizes
+      const int32_t ht = p->ntiles / 2, hg = p->ngroups / 2;
+      bool ok = p->ntiles % 2 == 0 && p->ngroups % 2 == 0;
+      for (int32_t t = 0; ok && t < ht; ++t) {
+        const TileItem &a = tiles[t], &b = tiles[t + ht];
+        ok = b.start == a.start + p->in_N && b.len == a.len && b.set == a.set + num_sets &&
+             b.rel0 == a.rel0 && b.nb_lo == a.nb_lo && b.nb_hi == a.nb_hi &&
+             b.set_len == a.set_len && b.group == (a.group < 0 ? -1 : a.group + hg);
+      }
+      if (!ok) {
+        delete p;
+        return UH_ERR_ARG;
+      }
+    }
+    for (auto &items : passes) {
+      p->pass_items.push_back((int32_t)items.size());
+      bool wide = large_plan && items.size() <= 64;
+      for (const MergeItem &m : items) wide = wide || m.nch > BLOCK;
+      p->pass_wide.push_back(wide);
+    }
   }
-  p->group_fan = fs0[0];
-  p->ngroups = passes.empty() ? 0 : (int32_t)passes[0].size();
-  if (both) {
-    // the tile kernel derives each lower tile from its upper twin: check that
-    // the schedule's second half is the first half moved by (N, S, tiles/2,
-    // groups/2), which holds because the two halves have the same set sizes
-    const int32_t ht = p->ntiles / 2, hg = p->ngroups / 2;
-    bool ok = p->ntiles % 2 == 0 && p->ngroups % 2 == 0;
-    for (int32_t t = 0; ok && t < ht; ++t) {
-      const TileItem &a = tiles[t], &b = tiles[t + ht];
-      ok = b.start == a.start + p->in_N && b.len == a.len && b.set == a.set + num_sets &&
-           b.rel0 == a.rel0 && b.nb_lo == a.nb_lo && b.nb_hi == a.nb_hi &&
-           b.set_len == a.set_len && b.group == (a.group < 0 ? -1 : a.group + hg);
-    }
-    if (!ok) {
-      delete p;
-      return UH_ERR_ARG;
-    }
-  }
+  p->h_voff = voff;
+  p->h_tiles = tiles;
+  p->h_items = passes;
   int rc = UH_OK;
   std::vector<int64_t> so(voff.begin(), voff.end());
   rc = rc ? rc : dalloc(&p->d_set_start, so.size());
   rc = rc ? rc : upload(p->d_set_start, so);
-  rc = rc ? rc : dalloc(&p->d_tiles, tiles.size());
-  rc = rc ? rc : upload(p->d_tiles, tiles);
-  rc = rc ? rc : dalloc(&p->d_cnt0, tiles.size());
-  for (auto &items : passes) {
+  if (!tiles.empty()) {
+    rc = rc ? rc : dalloc(&p->d_tiles, tiles.size());
+    rc = rc ? rc : upload(p->d_tiles, tiles);
+  }
+  rc = rc ? rc : dalloc(&p->d_cnt0, (size_t)p->ntiles);
+  for (size_t k = 0; k < p->pass_items.size(); ++k) {
     if (rc) break;
-    MergeItem *di = nullptr;
+    if (!passes.empty()) {
+      MergeItem *di = nullptr;
+      rc = rc ? rc : dalloc(&di, passes[k].size());
+      rc = rc ? rc : upload(di, passes[k]);
+      p->d_items.push_back(di);
+    }
     int32_t *dcnt = nullptr;
-    rc = rc ? rc : dalloc(&di, items.size());
-    rc = rc ? rc : upload(di, items);
-    rc = rc ? rc : dalloc(&dcnt, items.size());
-    p->d_items.push_back(di);
+    rc = rc ? rc : dalloc(&dcnt, (size_t)p->pass_items[k]);
     p->d_cnt.push_back(dcnt);
-    p->pass_items.push_back((int32_t)items.size());
-    // the wide workgroup (twice the threads and the LDS, one per compute
-    // unit) for more than BLOCK children, and in a large plan for a pass of
-    // few items, whose merges are large and latency-bound
-    bool wide = large_plan && items.size() <= 64;
-    for (const MergeItem &m : items) wide = wide || m.nch > BLOCK;
-    p->pass_wide.push_back(wide);
   }
   if (!rc && (flags & UH_FLAG_UNSORTED)) {
     p->unsorted = true;
@@ -1879,11 +2318,11 @@ int upper_hull_plan_config(const upper_hull_plan *plan, upper_hull_config *confi
   return UH_OK;
 }
 
-int upper_hull_plan_launches(const upper_hull_plan *plan) {
+int upper_hull_plan_launches(const upper_hull_plan *plan, int32_t with_stats) {
   if (!plan) return UH_ERR_ARG;
   const int sort = plan->unsorted && plan->rs.nblocks > 0 ? 5 * uh_rs::RS_PASSES : 0;
-  return sort + (int)plan->has_empty + (plan->ntiles > 0) + (int)plan->pass_items.size() +
-         (plan->unsorted ? 1 : 0);
+  return sort + (int)(plan->has_empty || with_stats) + (plan->ntiles > 0) +
+         (int)plan->pass_items.size() + (plan->unsorted ? 1 : 0);
 }
 
 int upper_hull_plan_set_probe(upper_hull_plan *plan, hipEvent_t before,
@@ -1923,10 +2362,12 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
   if (!(p->flags & UH_FLAG_GRAPH)) return enqueue_run(p, A, stream);
 
   std::lock_guard<std::mutex> lock(p->mu);
-  auto key = std::make_tuple((const void *)points, (void *)out_idx, (void *)out_counts,
-                             (void *)stats);
-  auto itg = p->graphs.find(key);
-  if (itg == p->graphs.end()) {
+  const auto key = std::make_tuple((const void *)points, (void *)out_idx, (void *)out_counts,
+                                   (void *)stats);
+  size_t at = p->graphs.size();
+  for (size_t k = 0; k < p->graphs.size(); ++k)
+    if (p->graphs[k].first == key) at = k;
+  if (at == p->graphs.size()) {
     if (!p->cap_stream &&
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return UH_ERR_HIP;
@@ -1942,9 +2383,124 @@ int upper_hull_plan_run(upper_hull_plan *p, const float *points, int32_t *out_id
     const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ie != hipSuccess) return UH_ERR_HIP;
-    itg = p->graphs.emplace(key, ex).first;
+    if (p->graphs.size() >= upper_hull_plan::GRAPH_CACHE) {  // drop the least recently used
+      // its earlier launches are ordered before this run's on their streams;
+      // destroying the executable does not cancel them
+      (void)hipGraphExecDestroy(p->graphs.front().second);
+      p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.emplace_back(key, ex);
+    at = p->graphs.size() - 1;
+  } else if (at + 1 != p->graphs.size()) {  // most recently used goes last
+    auto e = p->graphs[at];
+    p->graphs.erase(p->graphs.begin() + (long)at);
+    p->graphs.push_back(e);
+    at = p->graphs.size() - 1;
   }
-  return hipGraphLaunch(itg->second, stream) == hipSuccess ? UH_OK : UH_ERR_HIP;
+  return hipGraphLaunch(p->graphs[at].second, stream) == hipSuccess ? UH_OK : UH_ERR_HIP;
+}
+
+int32_t upper_hull_plan_blocks(const upper_hull_plan *p, int32_t level, int64_t *ranges) {
+  if (!p || level < 0 || level > (int32_t)p->pass_items.size()) return UH_ERR_ARG;
+  const int32_t nb = level == 0 ? p->ntiles : p->pass_items[level - 1];
+  if (!ranges) return nb;
+  for (int32_t b = 0; b < nb; ++b) {
+    int64_t start, end;
+    if (p->in_S == 1) {
+      const SingleShape &sh = p->single;
+      if (level == 0) {
+        const int32_t v = b / sh.tiles, t = b - v * sh.tiles;
+        start = v * sh.n + (int64_t)t * sh.T;
+        end = std::min(start + sh.T, (v + 1) * sh.n);
+      } else {
+        const PassArgs &pa = sh.pass[level - 1];
+        const int32_t v = b / pa.items, i = b - v * pa.items;
+        start = v * sh.n + (int64_t)i * pa.fan * pa.stride;
+        end = std::min(start + (int64_t)pa.fan * pa.stride, (v + 1) * sh.n);
+      }
+    } else if (level == 0) {
+      start = p->h_tiles[b].start;
+      end = start + p->h_tiles[b].len;
+    } else {
+      const MergeItem &m = p->h_items[level - 1][b];
+      start = m.off;
+      end = std::min(m.off + (int64_t)m.nch * m.stride, p->h_voff[m.set + 1]);
+    }
+    ranges[2 * b] = start;
+    ranges[2 * b + 1] = end - start;
+  }
+  return nb;
+}
+
+int upper_hull_plan_trace(upper_hull_plan *p, const float *points, int32_t level,
+                          int32_t *out_idx, int32_t *out_counts, hipStream_t stream) {
+  if (!p || p->unsorted || !out_counts || level < 0 ||
+      level > (int32_t)p->pass_items.size() || (p->N > 0 && (!points || !out_idx)))
+    return UH_ERR_ARG;
+  if (((uintptr_t)points & 7u) != 0) return UH_ERR_ARG;
+  if (!p->trace_cnt) {
+    bool cap = false;
+    int rc = capturing(stream, &cap);
+    if (rc) return rc;
+    if (cap) return UH_ERR_CAPTURE;
+    rc = dalloc(&p->trace_cnt, (size_t)p->S);
+    if (rc) return rc;
+  }
+  RunArgs A;
+  A.pts = (const float2 *)points;
+  A.set_start = p->d_set_start;
+  A.ws_xy = p->ws_xy;
+  A.ws_idx = p->ws_idx;
+  A.set_status = p->set_status;
+  A.out_idx = out_idx;
+  A.out_counts = p->trace_cnt;
+  A.stats = nullptr;
+  A.n_total = p->N;
+  A.tile_len = p->T;
+  A.group_fan = p->group_fan;
+  A.tile_max = p->tile_max;
+  A.group_max = p->group_max;
+  A.one_set = p->in_S == 1;
+  A.flags = p->flags;
+  A.n_points = p->in_N;
+  A.lower_n = p->both ? p->in_N : 0;
+  A.lower_tiles = p->both ? p->ntiles / 2 : 0;
+  A.lower_groups = p->both ? p->ngroups / 2 : 0;
+  A.lower_sets = p->both ? p->in_S : 0;
+  Launch L = plan_launch(p, A, false);
+  L.npass = level;  // the tile pass and merge passes 1 .. level
+  L.probe_before = L.probe_after = nullptr;
+  int rc = enqueue(L, stream);
+  if (rc) return rc;
+  if (level < (int32_t)p->pass_items.size()) {
+    // the next pass reads the group maxima of this run: it would have cleared
+    // them at its sets' final merges, so clear them here
+    Launch Z = L;
+    Z.tile_grid = 0;
+    Z.npass = 0;
+    Z.init = true;
+    Z.init_groups = p->ngroups;
+    Z.A.out_counts = p->trace_cnt;
+    // (init also resets the run's status and the counts of empty sets)
+    const int32_t nb = level == 0 ? p->ntiles : p->pass_items[level - 1];
+    const PassArgs pa = level == 0 || p->in_S != 1 ? PassArgs{} : p->single.pass[level - 1];
+    const MergeItem *items = level == 0 || p->d_items.empty() ? nullptr : p->d_items[level - 1];
+    const int32_t *cnt = level == 0 ? p->d_cnt0 : p->d_cnt[level - 1];
+    hipLaunchKernelGGL(trace_kernel, dim3((unsigned)std::max(nb, 1)), dim3(64), 0, stream, A,
+                       level, p->in_S == 1 ? p->single.tiles : 0, p->d_tiles, items, pa, cnt,
+                       out_counts);
+    if (hipGetLastError() != hipSuccess) return UH_ERR_HIP;
+    return enqueue(Z, stream);
+  }
+  const int32_t nb = p->pass_items.empty() ? p->ntiles : p->pass_items.back();
+  const PassArgs pa = level == 0 || p->in_S != 1 ? PassArgs{} : p->single.pass[level - 1];
+  const MergeItem *items = level == 0 || p->d_items.empty() ? nullptr : p->d_items[level - 1];
+  const int32_t *cnt = level == 0 ? p->d_cnt0 : p->d_cnt[level - 1];
+  if (nb > 0)
+    hipLaunchKernelGGL(trace_kernel, dim3((unsigned)nb), dim3(64), 0, stream, A, level,
+                       p->in_S == 1 ? p->single.tiles : 0, p->d_tiles, items, pa, cnt,
+                       out_counts);
+  return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
 
 void upper_hull_plan_destroy(upper_hull_plan *plan) {
@@ -1962,25 +2518,22 @@ int upper_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_co
                hipStream_t stream) {
   if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx)))
     return UH_ERR_ARG;
-  upper_hull_plan *p = nullptr;
-  const int rc = single_plan(n, 0u, stream, &p);
-  if (rc) return rc;
-  return upper_hull_plan_run(p, points, out_idx, out_count, nullptr, stream);
+  if (((uintptr_t)points & 7u) != 0) return UH_ERR_ARG;
+  return run_single(points, n, false, out_idx, out_count, stream, nullptr, nullptr);
 }
 
 int convex_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_count,
                 hipStream_t stream) {
   if (n < 0 || n > INT32_MAX || !out_count || (n > 0 && (!points || !out_idx)))
     return UH_ERR_ARG;
-  upper_hull_plan *p = nullptr;
-  int rc = single_plan(n, UH_FLAG_BOTH_HOODS, stream, &p);
-  if (rc) return rc;
-  // both hoods into the plan's buffers, then one join pass into out_idx
-  rc = upper_hull_plan_run(p, points, p->hull_idx, p->hull_cnt, nullptr, stream);
+  if (((uintptr_t)points & 7u) != 0) return UH_ERR_ARG;
+  // both hoods into buffers in the workspace, then one join pass into out_idx
+  int32_t *hood_idx = nullptr, *hood_cnt = nullptr;
+  int rc = run_single(points, n, true, nullptr, nullptr, stream, &hood_idx, &hood_cnt);
   if (rc) return rc;
   const int64_t nb = std::min<int64_t>((n + 255) / 256, 1024);
   hipLaunchKernelGGL(hull_assemble_kernel, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256),
-                     0, stream, p->hull_idx, p->hull_cnt, n, out_idx, out_count);
+                     0, stream, hood_idx, hood_cnt, n, out_idx, out_count);
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
 
@@ -1990,27 +2543,53 @@ int upper_hull_batched(const float *points, const int64_t *set_offsets, int32_t 
   if (!set_offsets || num_sets < 1 || !out_counts) return UH_ERR_ARG;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
-  upper_hull_plan *p = nullptr;
+  bool cap = false;
+  int rc = capturing(stream, &cap);
+  if (rc) return rc;
+  CachedPlan *cp = nullptr;
+  auto key = std::make_pair(dev, std::vector<int64_t>(set_offsets, set_offsets + num_sets + 1));
   {
     std::lock_guard<std::mutex> lock(g_cache_mu);
-    auto key = std::make_pair(dev, std::vector<int64_t>(set_offsets, set_offsets + num_sets + 1));
+    if (!cap) reap_retired();
     auto it = g_batched_plans.find(key);
-    if (it != g_batched_plans.end()) {
-      p = it->second;
-    } else {
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return UH_ERR_HIP;
-      if (cs != hipStreamCaptureStatusNone) return UH_ERR_CAPTURE;
-      if (g_batched_plans.size() >= 8) {  // bounded cache: drop the oldest
-        upper_hull_plan_destroy(g_batched_plans.begin()->second);
-        g_batched_plans.erase(g_batched_plans.begin());
+    if (it == g_batched_plans.end()) {
+      if (cap) return UH_ERR_CAPTURE;
+      if (g_batched_plans.size() >= BATCHED_CACHE) {
+        // drop the least recently used layout that no call is using and no
+        // captured graph refers to; its memory is freed once its last run is done
+        auto victim = g_batched_plans.end();
+        for (auto v = g_batched_plans.begin(); v != g_batched_plans.end(); ++v)
+          if (v->second.in_use == 0 && !v->second.captured &&
+              (victim == g_batched_plans.end() || v->second.last_use < victim->second.last_use))
+            victim = v;
+        if (victim != g_batched_plans.end()) {
+          g_retired.push_back(victim->second);
+          g_batched_plans.erase(victim);
+          reap_retired();
+        }
       }
-      const int rc = upper_hull_plan_create(set_offsets, num_sets, nullptr, &p);
+      upper_hull_plan *p = nullptr;
+      rc = upper_hull_plan_create(set_offsets, num_sets, nullptr, &p);
       if (rc) return rc;
-      g_batched_plans.emplace(std::move(key), p);
+      it = g_batched_plans.emplace(std::move(key), CachedPlan{p}).first;
+    }
+    cp = &it->second;
+    cp->last_use = ++g_clock;
+    ++cp->in_use;
+    cp->captured = cp->captured || cap;
+  }
+  rc = upper_hull_plan_run(cp->plan, points, out_idx, out_counts, stats, stream);
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  if (!rc && !cap) {
+    if (!cp->done && hipEventCreateWithFlags(&cp->done, hipEventDisableTiming) != hipSuccess)
+      cp->done = nullptr;
+    if (cp->done && hipEventRecord(cp->done, stream) != hipSuccess) {
+      (void)hipEventDestroy(cp->done);
+      cp->done = nullptr;
     }
   }
-  return upper_hull_plan_run(p, points, out_idx, out_counts, stats, stream);
+  --cp->in_use;
+  return rc;
 }
 
 int upper_hull_autotune(const float *points, const int64_t *set_offsets,

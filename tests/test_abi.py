@@ -60,3 +60,19 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(uh, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         uh.load_library()
+
+
+def test_workspace_bytes_is_pure_arithmetic(lib):
+    # callable without a GPU; monotone in both bounds; about 12 bytes a point
+    # (16 with the convex hull's hood buffers); 0 for invalid bounds
+    f = uh.upper_hull_workspace_bytes
+    assert f(-1, 1) == 0 and f(10, 0) == 0
+    prev = 0
+    for m in (0, 1, 1023, 1024, 1025, 65536, 1 << 20, (1 << 20) + 1, 1 << 27):
+        b = f(m, 1)
+        assert b >= prev and b >= 12 * m
+        assert b <= 12 * m + 64 * 1024 + m // 8, (m, b)
+        assert f(m, 2) >= b + 4 * m
+        prev = b
+    assert f(1 << 27, 4096) > f(1 << 27, 1)
+    assert f(1 << 27, 1) % 256 == 0

@@ -36,7 +36,7 @@ def test_full_size_workload(name):
     d = torch.from_numpy(pts).cuda()
     out = torch.empty(N, dtype=torch.int32, device="cuda")
     cnt = torch.empty(S, dtype=torch.int32, device="cuda")
-    stats = torch.zeros((S, 2), dtype=torch.int64, device="cuda")
+    stats = uh.new_stats(S)
     plan.run(d, out, cnt, stats)
     torch.cuda.synchronize()
     got_cnt = cnt.cpu().numpy()

@@ -34,7 +34,7 @@ def both_hoods(pts, off, strip=0, fan_in=0, flags=0, with_stats=False):
     N, S = int(off[-1]), len(off) - 1
     out = torch.full((max(2 * N, 1),), -7, dtype=torch.int32, device="cuda")
     cnt = torch.full((2 * S,), -7, dtype=torch.int32, device="cuda")
-    stats = torch.zeros((2 * S, 2), dtype=torch.int64, device="cuda") if with_stats else None
+    stats = uh.new_stats(2 * S) if with_stats else None
     plan.run(_dev(pts), out, cnt, stats)
     torch.cuda.synchronize()
     res = (out.cpu().numpy(), cnt.cpu().numpy())

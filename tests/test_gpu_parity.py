@@ -47,7 +47,7 @@ def gpu_batched(pts, off, strip=0, fan_in=0, flags=0, with_stats=False):
     S = len(off) - 1
     out = torch.full((max(int(off[-1]), 1),), -7, dtype=torch.int32, device="cuda")
     cnt = torch.full((S,), -7, dtype=torch.int32, device="cuda")
-    stats = torch.zeros((S, 2), dtype=torch.int64, device="cuda") if with_stats else None
+    stats = uh.new_stats(S) if with_stats else None
     plan.run(d, out, cnt, stats)
     torch.cuda.synchronize()
     res = (out.cpu().numpy(), cnt.cpu().numpy())
@@ -477,7 +477,7 @@ def test_batched_call_without_a_plan():
         out, cnt = uh.upper_hull_batched(d, off)
         torch.cuda.synchronize()
         assert_batched_equal(pts, off, out.cpu().numpy(), cnt.cpu().numpy())
-    stats = torch.zeros((len(off) - 1, 2), dtype=torch.int64, device="cuda")
+    stats = uh.new_stats(len(off) - 1)
     out, cnt = uh.upper_hull_batched(d, off, stats=stats)
     torch.cuda.synchronize()
     st = stats.cpu().numpy()
