@@ -66,6 +66,8 @@ extern "C" {
 #define UH_ERR_WORKSPACE (-5) /* the workspace set with                    */
                               /* upper_hull_set_workspace is too small for */
                               /* this call                                  */
+#define UH_ERR_TOO_LARGE (-6) /* more points than upper_hull_noalloc's    */
+                              /* fixed scratch serves (UH_NOALLOC_MAX_N)   */
 #define UH_ERR_UNSORTED (-10) /* data: x decreases somewhere               */
 #define UH_ERR_RANGE (-11)    /* data: x outside [0,1], y outside [-1,1],  */
                               /*       or a NaN / infinity                 */
@@ -175,6 +177,26 @@ int upper_hull_set_workspace(void *device_ptr, size_t bytes);
  */
 int upper_hull(const float *points, int64_t n, int32_t *out_idx,
                int32_t *out_count, hipStream_t stream);
+
+/*
+ * Upper hood of points[0..n) without any allocation, for callers that cannot
+ * allocate device memory: code being captured into a graph, tight serving
+ * loops, harnesses that forbid hipMalloc.  Arguments, result and errors as
+ * for upper_hull; in addition n > UH_NOALLOC_MAX_N returns UH_ERR_TOO_LARGE
+ * and enqueues nothing.
+ * The working memory is a fixed device array inside the library (about
+ * 12 bytes per point of UH_NOALLOC_MAX_N, 25 MB), one per device, held from
+ * the library's first use on that device until the process ends; the call
+ * never allocates, frees or synchronises.  Its device address is looked up
+ * once per device, on the first call there (make that call outside a graph
+ * capture).  Every call on a device shares that device's array, and each
+ * call's last contents stay in it: calls that overlap in time on one device
+ * (different streams, or different host threads without ordering) race and
+ * give undefined results; calls on one stream never overlap.
+ */
+#define UH_NOALLOC_MAX_N (1 << 21)
+int upper_hull_noalloc(const float *points, int64_t n, int32_t *out_idx,
+                       int32_t *out_count, hipStream_t stream);
 
 /*
  * Convex hull of points[0..n), the 2-D hull the paper's title and abstract

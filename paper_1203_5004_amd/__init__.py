@@ -27,6 +27,8 @@ UH_ERR_ALLOC = -2
 UH_ERR_HIP = -3
 UH_ERR_CAPTURE = -4
 UH_ERR_WORKSPACE = -5
+UH_ERR_TOO_LARGE = -6
+UH_NOALLOC_MAX_N = 1 << 21
 UH_ERR_UNSORTED = -10
 UH_ERR_RANGE = -11
 UH_ERR_GRID = -12
@@ -40,7 +42,8 @@ UH_FLAG_NO_ELIMINATION = 32
 UH_FLAG_CHECK_SIGNS = 64
 
 EXPORTS = (
-    "upper_hull_status_string", "upper_hull", "convex_hull", "upper_hull_batched",
+    "upper_hull_status_string", "upper_hull", "upper_hull_noalloc", "convex_hull",
+    "upper_hull_batched",
     "upper_hull_workspace_bytes", "upper_hull_set_workspace",
     "upper_hull_plan_create",
     "upper_hull_plan_run", "upper_hull_plan_destroy", "upper_hull_plan_launches",
@@ -100,6 +103,8 @@ def load_library():
     lib.upper_hull_status_string.restype = ctypes.c_char_p
     lib.upper_hull.argtypes = [p, i64, p, p, p]
     lib.upper_hull.restype = ctypes.c_int
+    lib.upper_hull_noalloc.argtypes = [p, i64, p, p, p]
+    lib.upper_hull_noalloc.restype = ctypes.c_int
     lib.convex_hull.argtypes = [p, i64, p, p, p]
     lib.convex_hull.restype = ctypes.c_int
     lib.upper_hull_batched.argtypes = [p, p, i32, p, p, p, p]
@@ -178,6 +183,14 @@ def upper_hull(points, out_idx=None, out_count=None, stream=None):
     out_count[0] entries of out_idx are the corners, left to right (a
     negative count is a data-error status).  Asynchronous on `stream`."""
     return _single("upper_hull", points, out_idx, out_count, stream)
+
+
+def upper_hull_noalloc(points, out_idx=None, out_count=None, stream=None):
+    """As ``upper_hull``, in the library's fixed per-device scratch: the call
+    allocates no device memory (at most UH_NOALLOC_MAX_N points; calls that
+    overlap in time on one device race).  Pass out_idx / out_count to keep
+    the call itself free of allocations."""
+    return _single("upper_hull_noalloc", points, out_idx, out_count, stream)
 
 
 def convex_hull(points, out_idx=None, out_count=None, stream=None):

@@ -1694,7 +1694,26 @@ struct SingleLayout {
   size_t cnt[MAX_PASSES];
 };
 
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Workspace bytes that serve every single-set or batched-free call with at
+// most m points over at most s sets: tiles of T = 1024 points (each set adds
+// at most one partial tile); first-level items of at least 64 tiles (or one
+// per set); items of all later passes together at most the tiles; the parts'
+// 256-byte alignment; and, for two sets or more, the hood buffers of
+// convex_hull (4 bytes per point).
+constexpr size_t workspace_bound(size_t m, size_t s) {
+  const size_t tiles = (m + 1023) / 1024 + s;
+  const size_t groups = tiles / 64 + 1 + s;
+  size_t b = 0;
+  b += align256(4 * s);                          // status
+  b += align256(4 * GROUP_STRIDE * groups);      // group maxima
+  b += 2 * align256(4 * tiles);                  // tile maxima, tile counts
+  b += align256(4 * tiles) + MAX_PASSES * 256;   // pass counts
+  b += align256(4 * m) + align256(8 * m);        // corner indices and positions
+  if (s >= 2) b += align256(4 * m) + align256(4 * s);  // hood buffers
+  return b;
+}
 
 SingleLayout single_layout(const SingleShape &sh, bool hull_buffers) {
   SingleLayout L;
@@ -1934,8 +1953,11 @@ int single_workspace(size_t need, hipStream_t stream, void **out) {
 // One set of n points (with both hoods: its upper hood into out_idx[0 .. n),
 // out_count[0], and its lower hood into out_idx[n .. 2n), out_count[1]; the
 // hood buffers inside the workspace if hood_bufs is given).
+// fixed != nullptr: the working memory is fixed[0 .. fixed_bytes) instead of
+// a workspace (upper_hull_noalloc); a run that needs more is refused.
 int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int32_t *out_count,
-               hipStream_t stream, int32_t **hood_idx, int32_t **hood_cnt) {
+               hipStream_t stream, int32_t **hood_idx, int32_t **hood_cnt,
+               void *fixed = nullptr, size_t fixed_bytes = 0) {
   const int K = 16;
   bool large = false;
   const int64_t off[2] = {0, n};
@@ -1944,9 +1966,13 @@ int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int3
   single_shape(n, both, K, F, large, sh);
   const bool bufs = hood_idx != nullptr;
   const SingleLayout L = single_layout(sh, bufs);
-  void *base = nullptr;
-  int rc = single_workspace(L.total, stream, &base);
-  if (rc) return rc;
+  void *base = fixed;
+  if (fixed) {
+    if (L.total > fixed_bytes) return UH_ERR_TOO_LARGE;
+  } else {
+    const int rc = single_workspace(L.total, stream, &base);
+    if (rc) return rc;
+  }
   char *b = static_cast<char *>(base);
   if (bufs) {
     *hood_idx = reinterpret_cast<int32_t *>(b + L.hull_idx);
@@ -2000,6 +2026,36 @@ int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int3
   return enqueue(La, stream);
 }
 
+// ---- fixed scratch of upper_hull_noalloc
+// The working memory of upper_hull_noalloc: a device array of the library's
+// own, sized for UH_NOALLOC_MAX_N points, one copy per device, held until the
+// process ends.  Host code never passes its name to a kernel (on the host it
+// is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_BYTES = workspace_bound((size_t)UH_NOALLOC_MAX_N, 1);
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_DEVICES];  // device address of `scratch` per device (null: not yet)
+
+// The current device's copy of `scratch`: its address is looked up on the
+// device's first call and kept (no allocation: the array is part of the
+// loaded code object).
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return UH_ERR_HIP;
+  if (dev < 0 || dev >= NOALLOC_DEVICES) return UH_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return UH_ERR_HIP;
+    g_noalloc_ptr[dev] = ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return UH_OK;
+}
+
 // ---- cached plans of the batched call without a plan object
 struct CachedPlan {
   upper_hull_plan *plan = nullptr;
@@ -2046,6 +2102,7 @@ const char *upper_hull_status_string(int status) {
     case UH_ERR_HIP: return "HIP runtime error";
     case UH_ERR_CAPTURE: return "allocation needed while the stream is capturing";
     case UH_ERR_WORKSPACE: return "the workspace set is too small for this call";
+    case UH_ERR_TOO_LARGE: return "more points than upper_hull_noalloc's fixed scratch serves";
     case UH_ERR_UNSORTED: return "data error: x not non-decreasing";
     case UH_ERR_RANGE: return "data error: coordinate out of range or not finite";
     case UH_ERR_GRID: return "data error: coordinate not on the 2^-30 grid";
@@ -2055,22 +2112,7 @@ const char *upper_hull_status_string(int status) {
 
 size_t upper_hull_workspace_bytes(int64_t max_total_n, int32_t max_sets) {
   if (max_total_n < 0 || max_sets < 1 || max_total_n > ((int64_t)1 << 40)) return 0;
-  // A bound over every call that fits: tiles of T = 1024 points (each set
-  // adds at most one partial tile); first-level items of at least 64 tiles
-  // (or one per set); items of all later passes together at most the tiles;
-  // the parts' 256-byte alignment; and, for two sets or more, the hood
-  // buffers of convex_hull (4 bytes per point).
-  const size_t m = (size_t)max_total_n, s = (size_t)max_sets;
-  const size_t tiles = (m + 1023) / 1024 + s;
-  const size_t groups = tiles / 64 + 1 + s;
-  size_t b = 0;
-  b += align256(4 * s);                          // status
-  b += align256(4 * GROUP_STRIDE * groups);      // group maxima
-  b += 2 * align256(4 * tiles);                  // tile maxima, tile counts
-  b += align256(4 * tiles) + MAX_PASSES * 256;   // pass counts
-  b += align256(4 * m) + align256(8 * m);        // corner indices and positions
-  if (s >= 2) b += align256(4 * m) + align256(4 * s);  // hood buffers
-  return b;
+  return workspace_bound((size_t)max_total_n, (size_t)max_sets);
 }
 
 int upper_hull_set_workspace(void *device_ptr, size_t bytes) {
@@ -2520,6 +2562,18 @@ int upper_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_co
     return UH_ERR_ARG;
   if (((uintptr_t)points & 7u) != 0) return UH_ERR_ARG;
   return run_single(points, n, false, out_idx, out_count, stream, nullptr, nullptr);
+}
+
+int upper_hull_noalloc(const float *points, int64_t n, int32_t *out_idx, int32_t *out_count,
+                       hipStream_t stream) {
+  if (n < 0 || !out_count || (n > 0 && (!points || !out_idx))) return UH_ERR_ARG;
+  if (n > UH_NOALLOC_MAX_N) return UH_ERR_TOO_LARGE;
+  if (((uintptr_t)points & 7u) != 0) return UH_ERR_ARG;
+  void *ptr = nullptr;
+  const int rc = noalloc_scratch(&ptr);
+  if (rc) return rc;
+  return run_single(points, n, false, out_idx, out_count, stream, nullptr, nullptr, ptr,
+                    NOALLOC_BYTES);
 }
 
 int convex_hull(const float *points, int64_t n, int32_t *out_idx, int32_t *out_count,

@@ -44,6 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_status_strings(lib):
     assert uh.upper_hull_status_string(uh.UH_OK) == "ok"
     for code in (uh.UH_ERR_ARG, uh.UH_ERR_ALLOC, uh.UH_ERR_HIP, uh.UH_ERR_CAPTURE,
+                 uh.UH_ERR_WORKSPACE, uh.UH_ERR_TOO_LARGE,
                  uh.UH_ERR_UNSORTED, uh.UH_ERR_RANGE, uh.UH_ERR_GRID):
         s = uh.upper_hull_status_string(code)
         assert s and s != "unknown status"
