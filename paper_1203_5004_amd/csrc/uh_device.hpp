@@ -110,6 +110,29 @@ __device__ __forceinline__ int orient_sign(float2 p, float2 q, float2 r,
   return orient_sign(p.x, p.y, q.x, q.y, r.x, r.y, cnt, fe);
 }
 
+// True only where the FP32 filter of orient_sign certifies that r lies
+// strictly right of p -> q (strictly below the line, for p.x < q.x); an
+// undecided case gives false.  For tests whose only use of a true answer is
+// to drop a point that cannot be a corner, so that undecided points are
+// simply kept and no exact evaluation is needed.  With force_exact (the
+// ablation that sends every test down the exact path) the exact sign
+// decides instead.
+__device__ __forceinline__ bool surely_below(float2 p, float2 q, float2 r, OrientCount &cnt,
+                                             bool force_exact) {
+#pragma clang fp contract(off)
+  if (force_exact) return orient_sign(p, q, r, cnt, true) < 0;
+  cnt.evals++;
+  const float dx1 = q.x - p.x, dy1 = q.y - p.y;
+  const float dx2 = r.x - p.x, dy2 = r.y - p.y;
+  const float l = dx1 * dy2;
+  const float rr = dy1 * dx2;
+  const float det = l - rr;
+  const float bound = (__builtin_fabsf(l) + __builtin_fabsf(rr)) * 0x1p-22f;
+  const bool below = det < -bound;
+  if (cnt.check && below && orient_int128(p.x, p.y, q.x, q.y, r.x, r.y) >= 0) cnt.sign_errors++;
+  return below;
+}
+
 // g(p, q_j): where corner j of the hood Q lies relative to the corner q'
 // that supports the tangent from p (p strictly left of Q):
 //   LOW   if q_{j+1} is on or above line p -> q_j   (q' is further right),
@@ -261,6 +284,86 @@ __device__ __forceinline__ void bridge_search(PT P, int hp, PT Q, int hq,
   }
 }
 
+// The bridge test of mam5 on one pair: true iff P[i] and Q[j] are each
+// other's tangent corner, g(P[i], Q[j]) = f(Q[j], P[i]) = EQUAL (with the tie
+// rules of g_classify / f_classify the pair is unique).  A missing neighbour
+// takes no test: it would compare a corner with itself, an exact zero that
+// the filter cannot certify.
+template <class PT>
+__device__ __forceinline__ bool bridge_pair(PT P, int hp, PT Q, int hq, int i, int j,
+                                            OrientCount &oc, bool fe) {
+  const int im = i > 0 ? i - 1 : 0, ip = i + 1 < hp ? i + 1 : i;
+  const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < hq ? j + 1 : j;
+  const float2 pi = P[i], pp = P[im], pn = P[ip];
+  const float2 qj = Q[j], qp = Q[jm], qn = Q[jp];
+  const bool g_eq = !(j + 1 < hq && orient_sign(pi, qj, qn, oc, fe) >= 0) &&
+                    !(j > 0 && orient_sign(pi, qj, qp, oc, fe) > 0);
+  return g_eq && !(i + 1 < hp && orient_sign(pi, qj, pn, oc, fe) > 0) &&
+         !(i > 0 && orient_sign(pi, qj, pp, oc, fe) >= 0);
+}
+
+// The bridge of two hoods (as bridge_search, same lanes), looked for first
+// next to the junction, where it nearly always lies once the hoods are
+// large and smooth (the late rounds of hull-heavy data); only if it is not
+// found there does the sampled search run.
+//  - With 8 lanes or more: P's last wp corners against Q's first wq, one
+//    pair per lane (wp * wq = L), each pair given mam5's test (bridge_pair).
+//  - With fewer: the group's first lane walks from the junction, at most
+//    WALK_MAX steps: Q's corner moves right while the next one is on or
+//    above the line P[a] -> Q[b] (g is LOW), P's moves left while the
+//    previous one is on or above it (f is HIGH).  On x-separated upper
+//    hoods such moves never make g HIGH or f LOW, so a walk that stops
+//    ends on the bridge; the end pair is checked with bridge_pair all the
+//    same, and a walk cut off by the step limit is not used.
+constexpr int WALK_MAX = 16;
+
+template <class PT>
+__device__ __forceinline__ void bridge_find(PT P, int hp, PT Q, int hq, int L, int t, int base,
+                                            int &out_a, int &out_b, OrientCount &cnt, bool fe) {
+  if (L < 8) {
+    int wa = hp - 1, wb = 0, ok = 0;
+    if (t == 0) {
+      int steps = 0;
+      bool moved = true;
+      while (moved && steps < WALK_MAX) {
+        moved = false;
+        while (wb + 1 < hq && steps < WALK_MAX &&
+               orient_sign(P[wa], Q[wb], Q[wb + 1], cnt, fe) >= 0) {
+          ++wb;
+          ++steps;
+          moved = true;
+        }
+        while (wa > 0 && steps < WALK_MAX && orient_sign(P[wa], Q[wb], P[wa - 1], cnt, fe) >= 0) {
+          --wa;
+          ++steps;
+          moved = true;
+        }
+      }
+      ok = bridge_pair(P, hp, Q, hq, wa, wb, cnt, fe) ? 1 : 0;
+    }
+    ok = __shfl(ok, base, 64);
+    if (ok) {
+      out_a = __shfl(wa, base, 64);
+      out_b = __shfl(wb, base, 64);
+      return;
+    }
+  } else {
+    const int lg = 31 - __builtin_clz((unsigned)L);
+    const int lgq = lg >> 1;  // wq = 2^floor(lg / 2), wp = L / wq
+    const int i = hp - 1 - (t >> lgq), j = t & ((1 << lgq) - 1);
+    const bool hit = i >= 0 && j < hq && bridge_pair(P, hp, Q, hq, i, j, cnt, fe);
+    const uint64_t gm = L == 64 ? ~0ull : ((1ull << L) - 1ull);
+    const uint64_t m = (__ballot(hit) >> base) & gm;
+    if (m) {
+      const int k = __builtin_ctzll(m);
+      out_a = hp - 1 - (k >> lgq);
+      out_b = k & ((1 << lgq) - 1);
+      return;
+    }
+  }
+  bridge_search<PT>(P, hp, Q, hq, L, t, base, out_a, out_b, cnt, fe);
+}
+
 // Orders LDS accesses of one wave: all lanes' earlier accesses are done
 // before any later one (a wave runs in lockstep; this stops the compiler
 // from moving LDS operations across the point).
@@ -356,19 +459,7 @@ __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
       if (r < npair) {
         i = (int)(((float)r + 0.5f) * rq);
         j = r - i * hq;
-        // g(P[i], Q[j]) and f(Q[j], P[i]) as in g_classify / f_classify,
-        // with the six corners read at once and all four tests evaluated
-        const int im = i > 0 ? i - 1 : 0, ip = i + 1 < hp ? i + 1 : i;
-        const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < hq ? j + 1 : j;
-        const float2 pi = xy[bp + i], pp = xy[bp + im], pn = xy[bp + ip];
-        const float2 qj = xy[bq + j], qp = xy[bq + jm], qn = xy[bq + jp];
-        // (a missing neighbour takes no test: it would compare a corner with
-        // itself, an exact zero that the filter cannot certify)
-        const bool g_eq = !(j + 1 < hq && orient_sign(pi, qj, qn, oc, fe) >= 0) &&
-                          !(j > 0 && orient_sign(pi, qj, qp, oc, fe) > 0);
-        const bool f_eq = !(i + 1 < hp && orient_sign(pi, qj, pn, oc, fe) > 0) &&
-                          !(i > 0 && orient_sign(pi, qj, pp, oc, fe) >= 0);
-        hit = g_eq && f_eq;
+        hit = bridge_pair<const float2 *>(xy + bp, hp, xy + bq, hq, i, j, oc, fe);
       }
       const uint64_t m = (__ballot(hit) >> gbase) & gmask;
       if (m) {
@@ -379,7 +470,7 @@ __device__ __forceinline__ void merge_blocks(float2 *xy, ID *id, int bp, int hp,
       }
     }
   } else {
-    bridge_search<const float2 *>(xy + bp, hp, xy + bq, hq, G, t, gbase, a, b, oc, fe);
+    bridge_find<const float2 *>(xy + bp, hp, xy + bq, hq, G, t, gbase, a, b, oc, fe);
   }
   const int np = a + 1, nq = hq - b;
   nc = np + nq;

@@ -489,7 +489,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
   // float32, a guess that decides nothing but whether to test) on which side
   // the first point of its strip lies, and the tile runs the exact test if
   // 48 lanes find theirs below (not on the noise of a nearly straight run).
-  bool chord_ran = false;
+  bool chord_ran = false, nb_ran = false;
   if (!noelim) {
     const int ll = it.len - 1, lane_l = ll / K, il = ll % K;
     const float2 tf = make_float2(readlane(p[0].x, 0), readlane(p[0].y, 0));
@@ -508,8 +508,53 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
             keep &= ~(1u << i);
       }
     }
+    // Neighbour chords: the points of each strip against the segment joining
+    // a point of the strip before it and a point of the strip after it (real
+    // points of the set; tested only for points strictly between them in x).
+    // Seen at the scale of a strip, a hull-heavy arc or parabola is a nearly
+    // straight run of noisy points.  Each strip offers as its witness the
+    // point highest above the local direction of the run (the line through
+    // the first points of its two neighbouring strips): such points lie at
+    // the top of the noise, and most of the strip between two of them lies
+    // under their segment.  The choice is a float32 guess (any real point is
+    // a valid witness); the test drops a point only where the FP32 filter
+    // certifies it strictly below the segment, and keeps it otherwise.  On a
+    // strongly curved run the strip lies above the segment and the tile
+    // skips the test (the same float32 guess as above, 16 lanes).
+    {
+      const int my_n = min(max(it.len - lane * K, 0), K);
+      const float dxs = dpp<DPP_WAVE_SHL1>(p[0].x, p[0].x) - dpp<DPP_WAVE_SHR1>(p[0].x, p[0].x);
+      const float dys = dpp<DPP_WAVE_SHL1>(p[0].y, p[0].y) - dpp<DPP_WAVE_SHR1>(p[0].y, p[0].y);
+      float2 m = p[0];
+      float best = p[0].y * dxs - p[0].x * dys;
+#pragma unroll
+      for (int i = 1; i < K; ++i) {
+        const float sc = p[i].y * dxs - p[i].x * dys;
+        if (i < my_n && sc > best) {
+          best = sc;
+          m = p[i];
+        }
+      }
+      const float2 ma = make_float2(dpp<DPP_WAVE_SHR1>(0.0f, m.x), dpp<DPP_WAVE_SHR1>(0.0f, m.y));
+      const float2 mb = make_float2(dpp<DPP_WAVE_SHL1>(0.0f, m.x), dpp<DPP_WAVE_SHL1>(0.0f, m.y));
+      const bool nb_ok = lane >= 1 && lane <= 62 && (lane + 1) * K < it.len;
+      const float est = (mb.x - ma.x) * (p[0].y - ma.y) - (mb.y - ma.y) * (p[0].x - ma.x);
+      if (__builtin_popcountll(__ballot(nb_ok && est < 0.0f)) >= 16) {
+        nb_ran = true;
+        if (nb_ok) {
+#pragma unroll
+          for (int i = 0; i < K; ++i)
+            if (((keep >> i) & 1u) && ma.x < p[i].x && p[i].x < mb.x &&
+                surely_below(ma, mb, p[i], oc, fe))
+              keep &= ~(1u << i);
+        }
+      }
+    }
   }
-  if (((K != 16 && K != 32) || chord_ran) && !noelim) {
+  // After the neighbour chords the points left are few per strip but not
+  // few per tile (hull-heavy data): they go through the strip hoods and
+  // rounds below rather than to the merge kernel's serial chain.
+  if (((K != 16 && K != 32) || chord_ran) && !noelim && !nb_ran) {
     // few survivors leave as a sorted point list: ranks by a wave prefix sum
     // (with strips of 16 or 32 the height test's survivors were counted
     // already; only the chord tests can have left few)
@@ -597,19 +642,12 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
   flush_wave_stats(A, it.set, oc);
 }
 
-template <int K, bool BOTH>
-__global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
-                                                  int32_t *cnt_out) {
-  constexpr int S = K;       // a strip's slot in LDS: K points, no padding
-  constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
-  constexpr float PAD_X = TILE_PAD_X, PAD_Y = TILE_PAD_Y;
-  __shared__ __attribute__((aligned(16))) float2 sxy[64 * S];
-  __shared__ uint16_t sid[64 * S];
-  __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
-
-  const int tile = blockIdx.x;
+// The tile a wave works on: from the table, or in a single-set run from
+// its index (tile t of the only set, ntiles tiles in all).
+__device__ __forceinline__ TileItem tile_item(const RunArgs &A, const TileItem *items, int tile,
+                                              int ntiles) {
   TileItem it;
-  if (A.one_set) {  // tile t of the only set: no item to fetch
+  if (A.one_set) {
     it.start = (int64_t)tile * A.tile_len;
     it.len = (int32_t)min((int64_t)A.tile_len, A.n_points - it.start);
     it.set = 0;
@@ -617,47 +655,86 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     it.nb_lo = (int16_t)min(16, it.rel0);
     it.nb_hi = (int16_t)min((int64_t)16, A.n_points - it.start - it.len);
     it.set_len = (int32_t)A.n_points;
-    it.group = gridDim.x == 1 ? -1 : tile / A.group_fan;
+    it.group = ntiles == 1 ? -1 : tile / A.group_fan;
   } else {
     it = items[tile];
   }
-  const int lane = threadIdx.x;
-  const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
-  const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
-  const float2 *src = A.pts + it.start;
+  return it;
+}
 
-  // ---- 1. load.  Every load of the tile is issued before the first wait:
-  // the tile's points, then (unconditionally, at clamped addresses) the
-  // witnesses from the neighbouring tiles of the same set -- the maximum y
-  // of up to 16 points just before the tile and of up to 16 just after it
-  // (lanes 0-15, two points each) -- and the set's point before the tile.
-  float4 v[NV];
+// Everything a tile reads from global memory: its points (a partial tile
+// padded with points right of and below every valid point), up to 16
+// witness points on either side of it (lanes 0-15, two each: their y), the
+// set's first and last point and the set's point just before the tile.
+template <int K>
+struct TileLoad {
+  float4 v[K / 2];
+  float y0, y1;
+  float2 set_first, set_last;
+  float prev_x;
+};
+
+// Issues every load of tile `it` without waiting for any of them.
+template <int K>
+__device__ __forceinline__ void tile_load(const RunArgs &A, const TileItem &it, TileLoad<K> &L) {
+  constexpr int NV = K / 2;
+  constexpr float PAD_X = TILE_PAD_X, PAD_Y = TILE_PAD_Y;
+  const int lane = threadIdx.x;
+  const float2 *src = A.pts + it.start;
   const bool full = it.len == 64 * K && (((uintptr_t)src) & 15u) == 0;
   if (full) {
     // full, 16-byte aligned tile (the common case): no per-element tests
     const float4 *src4 = reinterpret_cast<const float4 *>(__builtin_assume_aligned(src, 16));
 #pragma unroll
-    for (int r = 0; r < NV; ++r) v[r] = src4[lane + 64 * r];
+    for (int r = 0; r < NV; ++r) L.v[r] = src4[lane + 64 * r];
   } else {
     const bool al = (((uintptr_t)src) & 15u) == 0;
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
       const int e = 2 * (lane + 64 * r);
-      v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
+      L.v[r] = make_float4(PAD_X, PAD_Y, PAD_X, PAD_Y);
       if (e + 1 < it.len) {
         if (al) {
-          v[r] = *reinterpret_cast<const float4 *>(src + e);
+          L.v[r] = *reinterpret_cast<const float4 *>(src + e);
         } else {
           const float2 a = src[e], b = src[e + 1];
-          v[r] = make_float4(a.x, a.y, b.x, b.y);
+          L.v[r] = make_float4(a.x, a.y, b.x, b.y);
         }
       } else if (e < it.len) {
         const float2 a = src[e];
-        v[r].x = a.x;
-        v[r].y = a.y;
+        L.v[r].x = a.x;
+        L.v[r].y = a.y;
       }
     }
   }
+  // witnesses: unconditionally, at clamped addresses
+  const int64_t wlo = it.start - it.nb_lo, whi = it.start + it.len + it.nb_hi;
+  const int64_t e = lane < 8 ? it.start - 16 + 2 * lane : it.start + it.len + 2 * (lane - 8);
+  const bool ok0 = lane < 16 && (lane < 8 ? e >= wlo : e < whi);
+  const bool ok1 = lane < 16 && (lane < 8 ? e + 1 >= wlo : e + 1 < whi);
+  L.y0 = A.pts[ok0 ? e : it.start].y;
+  L.y1 = A.pts[ok1 ? e + 1 : it.start].y;
+  const int64_t set0 = it.start - it.rel0;
+  L.set_first = A.pts[set0];
+  L.set_last = A.pts[set0 + it.set_len - 1];
+  L.prev_x = A.pts[it.start - (it.rel0 > 0 ? 1 : 0)].x;
+}
+
+// Steps 1 (checks, strips) to 5 of one tile whose loads are in L.
+template <int K, bool BOTH>
+__device__ __forceinline__ void tile_process(const RunArgs &A, const TileItem &it, int tile,
+                                             int32_t *cnt_out, const TileLoad<K> &L,
+                                             float2 *sxy, uint16_t *sid, int2 *sblk) {
+  constexpr int S = K;       // a strip's slot in LDS: K points, no padding
+  constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
+  const int lane = threadIdx.x;
+  const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
+  const bool validate = (A.flags & UH_FLAG_NO_VALIDATE) == 0;
+  const float2 *src = A.pts + it.start;
+  const bool full = it.len == 64 * K && (((uintptr_t)src) & 15u) == 0;
+  float4 v[NV];
+#pragma unroll
+  for (int r = 0; r < NV; ++r) v[r] = L.v[r];
   float w0, w1;  // this lane's two witness heights (-2: none)
   float m0 = -2.0f, m1 = -2.0f;  // ... mirrored, for the lower hood
   {
@@ -665,18 +742,15 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     const int64_t e = lane < 8 ? it.start - 16 + 2 * lane : it.start + it.len + 2 * (lane - 8);
     const bool ok0 = lane < 16 && (lane < 8 ? e >= wlo : e < whi);
     const bool ok1 = lane < 16 && (lane < 8 ? e + 1 >= wlo : e + 1 < whi);
-    const float y0 = A.pts[ok0 ? e : it.start].y, y1 = A.pts[ok1 ? e + 1 : it.start].y;
-    w0 = ok0 ? y0 : -2.0f;
-    w1 = ok1 ? y1 : -2.0f;
+    w0 = ok0 ? L.y0 : -2.0f;
+    w1 = ok1 ? L.y1 : -2.0f;
     if constexpr (BOTH) {
-      m0 = ok0 ? -y0 : -2.0f;
-      m1 = ok1 ? -y1 : -2.0f;
+      m0 = ok0 ? -L.y0 : -2.0f;
+      m1 = ok1 ? -L.y1 : -2.0f;
     }
   }
-  const int64_t set0 = it.start - it.rel0;
-  float2 set_first = A.pts[set0], set_last = A.pts[set0 + it.set_len - 1];  // chord of the set
-  const float prev_x = A.pts[it.start - (it.rel0 > 0 ? 1 : 0)].x;
-  const float prev_tile_x = validate && it.rel0 > 0 ? prev_x : -1.0f;  // -1: below every valid x
+  float2 set_first = L.set_first, set_last = L.set_last;  // chord of the set
+  const float prev_tile_x = validate && it.rel0 > 0 ? L.prev_x : -1.0f;  // -1: below every valid x
 
   int err = 0;
   bool bad = false;  // some check failed, or the quick checks cannot vouch
@@ -805,6 +879,21 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
     tile_hood<K>(A, lo, tile + A.lower_tiles, cnt_out, p, mb_before, mb_after, set_first,
                  set_last, err, fe, sxy, sid, sblk);
   }
+}
+
+// The tile pass: one wave per tile.
+template <int K, bool BOTH>
+__global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
+                                                  int32_t *cnt_out, int32_t ntiles) {
+  __shared__ __attribute__((aligned(16))) float2 sxy[64 * K];
+  __shared__ uint16_t sid[64 * K];
+  __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
+
+  const int tile = blockIdx.x;
+  const TileItem it = tile_item(A, items, tile, ntiles);
+  TileLoad<K> ld;
+  tile_load<K>(A, it, ld);
+  tile_process<K, BOTH>(A, it, tile, cnt_out, ld, sxy, sid, sblk);
 }
 
 // ---------------------------------------------------------------- merges
@@ -1380,7 +1469,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       Q.c0 += qs;
       const int L = G < 64 ? G : 64;
       if (hp > 0 && hqe > 0 && t < L)
-        bridge_search<Rope>(P, hp, Q, hqe, L, t, (tid & 63) - t, a, b, oc, fe);
+        bridge_find<Rope>(P, hp, Q, hqe, L, t, (tid & 63) - t, a, b, oc, fe);
       b += qs;  // Q's first kept corner
     }
     __syncthreads();  // searches done; every merge's result to sres
@@ -1770,10 +1859,11 @@ int enqueue(const Launch &L, hipStream_t stream) {
                        L.init_groups, A);
   }
   if (L.tile_grid > 0) {
-    const dim3 grid(L.tile_grid), blk(64);
+    const dim3 blk(64);
     if (L.probe_before && hipEventRecord(L.probe_before, stream) != hipSuccess) return UH_ERR_HIP;
-#define UH_TILE(KK, BB) \
-  hipLaunchKernelGGL((tile_kernel<KK, BB>), grid, blk, 0, stream, A, L.tiles, L.cnt0)
+#define UH_TILE(KK, BB)                                                                     \
+  hipLaunchKernelGGL((tile_kernel<KK, BB>), dim3(L.tile_grid), blk, 0, stream, A, L.tiles, \
+                     L.cnt0, L.tile_grid)
     switch (L.K * 2 + (L.both ? 1 : 0)) {
       case 8: UH_TILE(4, false); break;
       case 9: UH_TILE(4, true); break;
