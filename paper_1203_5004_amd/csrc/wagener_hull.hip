@@ -61,6 +61,7 @@ constexpr int VMAX_WIDE = 12000; // ... and the wide one (one per CU)
 // sorted point list, not yet a hood); the merge kernel makes it a hood.
 constexpr uint32_t POINTS_FLAG = 0x80000000u;
 constexpr int TILE_LIST_MAX = 64;  // most survivors a tile hands on as a list
+constexpr int SERIAL_MAX = 64;     // corners a merge finishes with the serial chain
 // A group's maximum owns a 256-byte line of its own, so the atomics of the
 // tiles of different groups never queue behind one another.
 constexpr int GROUP_STRIDE = 64;
@@ -1138,6 +1139,9 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   __syncthreads();
 
   if (V <= VMX) {
+    constexpr int NW = BLK / 64;  // waves
+    bool serial = false;          // the serial chain finishes this merge
+    int nleaf_w = 0;              // leaves of this wave's rounds
     // ---- gather: the prefetched entries to their places, then thread k
     // copies whatever child k has beyond them, eight loads in flight
     if (!known_max) {
@@ -1332,51 +1336,86 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       if (lane == 0) swave[w] = __builtin_popcountll(ne);
       __syncthreads();
       int before = 0, total = 0;
-      for (int k = 0; k < BLK / 64; ++k) {
+      for (int k = 0; k < NW; ++k) {
         before += k < w ? swave[k] : 0;
         total += swave[k];
       }
-      if (total <= 64) {  // all leaves to wave 0's rounds, back to back
-        if (kept > 0)
-          sblk[before + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
-      } else {            // 64 leaf slots per wave, then wave 0 joins them
-        if (kept > 0)
-          sblk[(w << 6) + __builtin_popcountll(ne & ((1ull << lane) - 1ull))] = make_int2(o, kept);
+      // Few corners left: the serial chain finishes the merge (the serial
+      // hood of the work-optimal variant's strips); its depth beats that of
+      // log2(leaves) rounds.  Otherwise the leaves are dealt to the waves in
+      // contiguous runs of at most `per`, each wave runs the rounds over its
+      // run, and the wave hoods are joined pairwise in log2(waves) rounds.
+      int vk = kept;
+      for (int d = 1; d < 64; d <<= 1) vk += __shfl_xor(vk, d, 64);
+      if (lane == 0) sres[w] = make_int2(vk, 0);
+      __syncthreads();
+      int vsum = 0;
+      for (int k = 0; k < NW; ++k) vsum += sres[k].x;
+      serial = !noelim && vsum <= SERIAL_MAX;
+      const int per = total > 0 ? (total + NW - 1) / NW : 1;
+      if (kept > 0) {
+        const int li = before + __builtin_popcountll(ne & ((1ull << lane) - 1ull));
+        const int wv = li / per;
+        sblk[serial ? li : (wv << 6) + li - wv * per] = make_int2(o, kept);
       }
-      if (tid == 0) swave[BLK / 64] = total;
+      if (tid == 0) swave[NW] = total;
+      nleaf_w = min(max(total - w * per, 0), per);
     }
     __syncthreads();
-    const int total_leaves = swave[BLK / 64];
-    if (total_leaves > 64) wave_rounds(bxy, bid, sblk + (w << 6), swave[w], oc, fe);
-    __syncthreads();
-    if (w == 0) {
-      if (total_leaves == 0) {  // every child empty (possible on invalid data)
-        if (lane == 0) sblk[0] = make_int2(0, 0);
-        wave_sync();
-      } else if (total_leaves <= 64) {
-        wave_rounds(bxy, bid, sblk, total_leaves, oc, fe);
-      } else {
-        // the wave hoods (one per wave that had leaves), left to right
-        int nb0 = 0, nc0 = 0;
-        bool have = false;
-        for (int k = 0; k < BLK / 64; ++k) {
-          if (swave[k] == 0) continue;
-          const int2 Q = sblk[k << 6];
-          if (!have) {
-            nb0 = Q.x;
-            nc0 = Q.y;
-            have = true;
-            continue;
+    if (serial) {
+      if (tid == 0) {
+        // chain over the kept entries of the non-empty children (the
+        // leaves) in order, the stack from position 0: it never passes the
+        // entry being read
+        int cnt = 0;
+        float2 t1 = make_float2(0.f, 0.f), t2 = t1;
+        const int nl = swave[NW];
+        for (int k = 0; k < nl; ++k) {
+          const int2 lf = sblk[k];
+          const int ck = lf.y, ok = lf.x;
+          for (int j = 0; j < ck; ++j) {
+            const float2 r = bxy[ok + j];
+            const int32_t ri = bid[ok + j];
+            if (cnt >= 1 && r.x == t1.x) {
+              if (r.y <= t1.y) continue;  // the top hides r (ties: lower index)
+              --cnt;                      // r hides the top
+              t1 = t2;
+              if (cnt >= 2) t2 = bxy[cnt - 2];
+            }
+            while (cnt >= 2 && orient_sign(t2, t1, r, oc, fe) >= 0) {
+              --cnt;
+              t1 = t2;
+              if (cnt >= 2) t2 = bxy[cnt - 2];
+            }
+            bxy[cnt] = r;
+            bid[cnt] = ri;
+            t2 = t1;
+            t1 = r;
+            ++cnt;
           }
-          int nb, nc;
-          merge_blocks(bxy, bid, nb0, nc0, Q.x, Q.y, 6, lane, 0, nb, nc, oc, fe);
-          wave_sync();
-          nb0 = nb;
-          nc0 = nc;
         }
-        if (lane == 0) sblk[0] = make_int2(nb0, nc0);
-        wave_sync();
+        sblk[0] = make_int2(0, cnt);
       }
+      __syncthreads();
+    } else {
+      if (nleaf_w > 0) {
+        wave_rounds(bxy, bid, sblk + (w << 6), nleaf_w, oc, fe);
+      } else if (lane == 0) {
+        sblk[w << 6] = make_int2(0, 0);
+      }
+      __syncthreads();
+      for (int st = 1; st < NW; st <<= 1) {  // join the wave hoods pairwise
+        if ((w & (2 * st - 1)) == 0 && w + st < NW) {
+          const int2 P = sblk[w << 6], Q = sblk[(w + st) << 6];
+          int nb, nc;
+          merge_blocks(bxy, bid, P.x, P.y, Q.x, Q.y, 6, lane, 0, nb, nc, oc, fe);
+          wave_sync();
+          if (lane == 0) sblk[w << 6] = make_int2(nb, nc);
+        }
+        __syncthreads();
+      }
+    }
+    if (w == 0) {
       const int hb = sblk[0].x, hc = sblk[0].y;
       if (it.final_) {
         int32_t *dst = A.out_idx + set_base(A, it.set);
@@ -1490,20 +1529,26 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     }
     rescan();
   }
-  // the result: corner e lives in child l with cum[l] <= e < cum[l + 1]
+  // the result: corner e lives in child l with cum[l] <= e < cum[l + 1].  A
+  // thread's positions only grow, so its child is found by walking forward
+  // from the previous one (each child passed once) instead of a search.
   const int hc = cum[BLK];
-  const Rope R{A.ws_xy, cum, klo, it.off, it.stride, 0, nch, 0};  // reads the workspace
+  int lw = 0;
+  auto where = [&](int e) {
+    while (lw + 1 < nch && cum[lw + 1] <= e) ++lw;
+    return it.off + (int64_t)lw * it.stride + klo[lw] + (e - cum[lw]);
+  };
   if (it.final_) {
     int32_t *dst = A.out_idx + set_base(A, it.set);
-    for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {
-      int32_t vi[8];
+    for (int e0 = 0; e0 < hc; e0 += 16 * BLK) {  // sixteen loads in flight
+      int32_t vi[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int e = e0 + u * BLK + tid;
-        if (e < hc) vi[u] = A.ws_idx[R.where(e)];
+        if (e < hc) vi[u] = A.ws_idx[where(e)];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int e = e0 + u * BLK + tid;
         if (e < hc) dst[e] = vi[u];
       }
@@ -1525,7 +1570,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + u * BLK + tid;
         if (e < hc) {
-          const int64_t src = R.where(e);
+          const int64_t src = where(e);
           vx[u] = A.ws_xy[src];
           vi[u] = A.ws_idx[src];
         }
