@@ -586,7 +586,46 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
 
   // ---- 4. strip hoods, then rounds of Wagener merges over them
   int nleaf;
-  {
+  if (!noelim) {
+    // After the eliminations most strips keep a point or two: serial hoods
+    // of whole strips would leave up to 64 tiny leaves and six rounds of
+    // merges.  The survivors are compacted instead, in x order, into the
+    // LDS arrays (the strips' points are in registers by now) and cut into
+    // chunks of C consecutive survivors; lane l builds the serial hood of
+    // chunk l in place (the serial hoods of the work-optimal variant's
+    // strips, over survivors rather than over all points).  The chunk hoods
+    // are the leaves: every chunk keeps at least one corner.
+    const int nk = __builtin_popcount(keep);
+    int koff = nk;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(koff, o, 64);
+      if (lane >= o) koff += y;
+    }
+    const int nsurv = __shfl(koff, 63, 64);
+    koff -= nk;
+    wave_sync();  // every lane is done with the strips in LDS
+    {
+      int r = koff;
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        if ((keep >> i) & 1u) {
+          sxy[r] = p[i];
+          sid[r] = (uint16_t)(lane * K + i);
+          ++r;
+        }
+      }
+    }
+    wave_sync();
+    int C = 8;  // chunk length: at most 64 chunks
+    while (C * 64 < nsurv) C <<= 1;
+    nleaf = (nsurv + C - 1) / C;
+    if (lane < nleaf) {
+      const int b = lane * C;
+      const int cnt = chain_inplace(sxy + b, sid + b, min(C, nsurv - b), oc, fe);
+      sblk[lane] = make_int2(b, cnt);
+    }
+    wave_sync();
+  } else {
     // the serial strip hood over each strip's survivors, taken from the
     // registers in order; its stack overwrites the strip's LDS slot from
     // the start (in plain order); the non-empty strip hoods are the leaves
@@ -1363,38 +1402,62 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     }
     __syncthreads();
     if (serial) {
-      if (tid == 0) {
-        // chain over the kept entries of the non-empty children (the
-        // leaves) in order, the stack from position 0: it never passes the
-        // entry being read
+      if (w == 0) {
+        // the kept entries of the leaves, flattened: lane e < vk holds entry
+        // e (found from the leaves' prefix counts); the chain then reads the
+        // entries from the lanes, the same values in every lane, so it has
+        // no LDS latency but that of its stack (from position 0 of the LDS
+        // arrays; the entries are all in registers by then)
+        const int nl = swave[NW];
+        const int2 lf = lane < nl ? sblk[lane] : make_int2(0, 0);
+        int incl = lf.y;
+        for (int d = 1; d < 64; d <<= 1) {
+          const int y = __shfl_up(incl, d, 64);
+          if (lane >= d) incl += y;
+        }
+        const int vk = __shfl(incl, 63, 64);
+        int li = 0;  // the leaf of entry `lane`
+        for (int k = 0; k < nl; ++k) li += __shfl(incl, k, 64) <= lane ? 1 : 0;
+        li = min(li, 63);
+        const int excl = __shfl(incl - lf.y, li, 64), lo = __shfl(lf.x, li, 64);
+        float2 ex = make_float2(0.f, 0.f);
+        int32_t ei = 0;
+        if (lane < vk) {
+          ex = bxy[lo + lane - excl];
+          ei = bid[lo + lane - excl];
+        }
+        wave_sync();  // every entry is read before the stack overwrites them
+        OrientCount o1 = run_counter(A);
         int cnt = 0;
         float2 t1 = make_float2(0.f, 0.f), t2 = t1;
-        const int nl = swave[NW];
-        for (int k = 0; k < nl; ++k) {
-          const int2 lf = sblk[k];
-          const int ck = lf.y, ok = lf.x;
-          for (int j = 0; j < ck; ++j) {
-            const float2 r = bxy[ok + j];
-            const int32_t ri = bid[ok + j];
-            if (cnt >= 1 && r.x == t1.x) {
-              if (r.y <= t1.y) continue;  // the top hides r (ties: lower index)
-              --cnt;                      // r hides the top
-              t1 = t2;
-              if (cnt >= 2) t2 = bxy[cnt - 2];
-            }
-            while (cnt >= 2 && orient_sign(t2, t1, r, oc, fe) >= 0) {
-              --cnt;
-              t1 = t2;
-              if (cnt >= 2) t2 = bxy[cnt - 2];
-            }
+        for (int e = 0; e < vk; ++e) {
+          const float2 r = make_float2(readlane(ex.x, e), readlane(ex.y, e));
+          const int32_t ri = __builtin_amdgcn_readlane(ei, e);
+          if (cnt >= 1 && r.x == t1.x) {
+            if (r.y <= t1.y) continue;  // the top hides r (ties: lower index)
+            --cnt;                      // r hides the top
+            t1 = t2;
+            if (cnt >= 2) t2 = bxy[cnt - 2];
+          }
+          while (cnt >= 2 && orient_sign(t2, t1, r, o1, fe) >= 0) {
+            --cnt;
+            t1 = t2;
+            if (cnt >= 2) t2 = bxy[cnt - 2];
+          }
+          if (lane == 0) {
             bxy[cnt] = r;
             bid[cnt] = ri;
-            t2 = t1;
-            t1 = r;
-            ++cnt;
           }
+          t2 = t1;
+          t1 = r;
+          ++cnt;
         }
-        sblk[0] = make_int2(0, cnt);
+        if (lane == 0) {
+          sblk[0] = make_int2(0, cnt);
+          oc.evals += o1.evals;  // one lane counts the wave's tests
+          oc.fallbacks += o1.fallbacks;
+          oc.sign_errors += o1.sign_errors;
+        }
       }
       __syncthreads();
     } else {
