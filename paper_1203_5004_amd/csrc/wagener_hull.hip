@@ -61,7 +61,7 @@ constexpr int VMAX_WIDE = 12000; // ... and the wide one (one per CU)
 // sorted point list, not yet a hood); the merge kernel makes it a hood.
 constexpr uint32_t POINTS_FLAG = 0x80000000u;
 constexpr int TILE_LIST_MAX = 64;  // most survivors a tile hands on as a list
-constexpr int SERIAL_MAX = 64;     // corners a merge finishes with the serial chain
+constexpr int DIRECT_MAX = 64;     // corners a merge finishes by the direct corner test
 // A group's maximum owns a 256-byte line of its own, so the atomics of the
 // tiles of different groups never queue behind one another.
 constexpr int GROUP_STRIDE = 64;
@@ -1179,7 +1179,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
 
   if (V <= VMX) {
     constexpr int NW = BLK / 64;  // waves
-    bool serial = false;          // the serial chain finishes this merge
+    bool direct = false;          // this merge is finished by the direct corner test
     int nleaf_w = 0;              // leaves of this wave's rounds
     // ---- gather: the prefetched entries to their places, then thread k
     // copies whatever child k has beyond them, eight loads in flight
@@ -1379,9 +1379,10 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         before += k < w ? swave[k] : 0;
         total += swave[k];
       }
-      // Few corners left: the serial chain finishes the merge (the serial
-      // hood of the work-optimal variant's strips); its depth beats that of
-      // log2(leaves) rounds.  Otherwise the leaves are dealt to the waves in
+      // Few corners left: one wave finishes the merge by testing every
+      // corner against the hood's definition directly (a corner per lane),
+      // whose depth beats that of log2(leaves) rounds of merges.  Otherwise
+      // the leaves are dealt to the waves in
       // contiguous runs of at most `per`, each wave runs the rounds over its
       // run, and the wave hoods are joined pairwise in log2(waves) rounds.
       int vk = kept;
@@ -1390,24 +1391,21 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       __syncthreads();
       int vsum = 0;
       for (int k = 0; k < NW; ++k) vsum += sres[k].x;
-      serial = !noelim && vsum <= SERIAL_MAX;
+      direct = !noelim && vsum <= DIRECT_MAX;
       const int per = total > 0 ? (total + NW - 1) / NW : 1;
       if (kept > 0) {
         const int li = before + __builtin_popcountll(ne & ((1ull << lane) - 1ull));
         const int wv = li / per;
-        sblk[serial ? li : (wv << 6) + li - wv * per] = make_int2(o, kept);
+        sblk[direct ? li : (wv << 6) + li - wv * per] = make_int2(o, kept);
       }
       if (tid == 0) swave[NW] = total;
       nleaf_w = min(max(total - w * per, 0), per);
     }
     __syncthreads();
-    if (serial) {
+    if (direct) {
       if (w == 0) {
         // the kept entries of the leaves, flattened: lane e < vk holds entry
-        // e (found from the leaves' prefix counts); the chain then reads the
-        // entries from the lanes, the same values in every lane, so it has
-        // no LDS latency but that of its stack (from position 0 of the LDS
-        // arrays; the entries are all in registers by then)
+        // e (found from the leaves' prefix counts)
         const int nl = swave[NW];
         const int2 lf = lane < nl ? sblk[lane] : make_int2(0, 0);
         int incl = lf.y;
@@ -1426,38 +1424,41 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
           ex = bxy[lo + lane - excl];
           ei = bid[lo + lane - excl];
         }
-        wave_sync();  // every entry is read before the stack overwrites them
-        OrientCount o1 = run_counter(A);
-        int cnt = 0;
-        float2 t1 = make_float2(0.f, 0.f), t2 = t1;
+        wave_sync();  // every entry is read before the result overwrites them
+        // Lane c keeps entry c iff it is a corner of the hood of all vk
+        // entries, by the definition: no entry at its x is higher, or as
+        // high with a lower index; and either no entry lies strictly left
+        // (right) of it, or it lies strictly above the segment from its left
+        // tangent point (of the entries strictly left of it, the one with
+        // the least slope to it) to its right tangent point (of those
+        // strictly right, the one with the greatest slope from it), the
+        // segment that lies highest at its x among all that span it.  Every
+        // lane reads every entry from the lanes (the same values in all).
+        const float2 cp = ex;
+        bool hidden = lane >= vk, have_l = false, have_r = false;
+        float2 lt = cp, rt = cp;
         for (int e = 0; e < vk; ++e) {
-          const float2 r = make_float2(readlane(ex.x, e), readlane(ex.y, e));
-          const int32_t ri = __builtin_amdgcn_readlane(ei, e);
-          if (cnt >= 1 && r.x == t1.x) {
-            if (r.y <= t1.y) continue;  // the top hides r (ties: lower index)
-            --cnt;                      // r hides the top
-            t1 = t2;
-            if (cnt >= 2) t2 = bxy[cnt - 2];
+          const float2 q = make_float2(readlane(ex.x, e), readlane(ex.y, e));
+          const int32_t qi = __builtin_amdgcn_readlane(ei, e);
+          if (q.x == cp.x) {
+            hidden = hidden || q.y > cp.y || (q.y == cp.y && qi < ei);
+          } else if (q.x < cp.x) {
+            if (!have_l || orient_sign(lt, cp, q, oc, fe) > 0) lt = q;
+            have_l = true;
+          } else {
+            if (!have_r || orient_sign(cp, rt, q, oc, fe) > 0) rt = q;
+            have_r = true;
           }
-          while (cnt >= 2 && orient_sign(t2, t1, r, o1, fe) >= 0) {
-            --cnt;
-            t1 = t2;
-            if (cnt >= 2) t2 = bxy[cnt - 2];
-          }
-          if (lane == 0) {
-            bxy[cnt] = r;
-            bid[cnt] = ri;
-          }
-          t2 = t1;
-          t1 = r;
-          ++cnt;
         }
-        if (lane == 0) {
-          sblk[0] = make_int2(0, cnt);
-          oc.evals += o1.evals;  // one lane counts the wave's tests
-          oc.fallbacks += o1.fallbacks;
-          oc.sign_errors += o1.sign_errors;
+        const bool corner =
+            !hidden && (!have_l || !have_r || orient_sign(lt, rt, cp, oc, fe) > 0);
+        const uint64_t cm = __ballot(corner);
+        if (corner) {
+          const int r = lanes_below(cm);
+          bxy[r] = cp;
+          bid[r] = ei;
         }
+        if (lane == 0) sblk[0] = make_int2(0, __builtin_popcountll(cm));
       }
       __syncthreads();
     } else {
@@ -1519,23 +1520,34 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   float2 *const lxy = reinterpret_cast<float2 *>(lds_corners);
   if (in_lds) {
     __syncthreads();  // the chained counts
-    for (int e0 = 0; e0 < V; e0 += 8 * BLK) {  // shared by all threads
-      float2 v8[8];
-      int dst[8];
+    // a thread's positions only grow: its child, that child's slot minus its
+    // first position, its count and the next child's first position stay
+    // in registers and change when a position passes into the next child
+    int kw = 0, kend = nch > 1 ? soff[1] : INT32_MAX, kcnt = bcnt[0];
+    int64_t kbase = it.off;
+    for (int e0 = 0; e0 < V; e0 += 16 * BLK) {  // shared by all threads
+      float2 v8[16];
+      int dst[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int e = e0 + u * BLK + tid;
         dst[u] = -1;
         if (e < V) {
-          const int k = child_of<BLK>(soff, nch, e), j = e - soff[k];
-          if (j < bcnt[k]) {
-            v8[u] = A.ws_xy[it.off + (int64_t)k * it.stride + j];
+          if (e >= kend) {
+            do ++kw;
+            while (kw + 1 < nch && soff[kw + 1] <= e);
+            kbase = it.off + (int64_t)kw * it.stride - soff[kw];
+            kend = kw + 1 < nch ? soff[kw + 1] : INT32_MAX;
+            kcnt = bcnt[kw] + soff[kw];
+          }
+          if (e < kcnt) {
+            v8[u] = A.ws_xy[kbase + e];
             dst[u] = e;
           }
         }
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 16; ++u)
         if (dst[u] >= 0) lxy[dst[u]] = v8[u];
     }
   }
@@ -1596,10 +1608,17 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   // thread's positions only grow, so its child is found by walking forward
   // from the previous one (each child passed once) instead of a search.
   const int hc = cum[BLK];
-  int lw = 0;
+  int lw = 0;                                     // the child of the last position,
+  int64_t lbase = it.off + klo[0] - cum[0];       // its position minus its first rank,
+  int lend = nch > 1 ? cum[1] : INT32_MAX;        // and the rank where the next one starts
   auto where = [&](int e) {
-    while (lw + 1 < nch && cum[lw + 1] <= e) ++lw;
-    return it.off + (int64_t)lw * it.stride + klo[lw] + (e - cum[lw]);
+    if (e >= lend) {
+      do ++lw;
+      while (lw + 1 < nch && cum[lw + 1] <= e);
+      lbase = it.off + (int64_t)lw * it.stride + klo[lw] - cum[lw];
+      lend = lw + 1 < nch ? cum[lw + 1] : INT32_MAX;
+    }
+    return lbase + e;
   };
   if (it.final_) {
     int32_t *dst = A.out_idx + set_base(A, it.set);
