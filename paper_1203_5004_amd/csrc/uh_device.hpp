@@ -306,8 +306,20 @@ __device__ __forceinline__ bool bridge_pair(PT P, int hp, PT Q, int hq, int i, i
 // next to the junction, where it nearly always lies once the hoods are
 // large and smooth (the late rounds of hull-heavy data); only if it is not
 // found there does the sampled search run.
-//  - With 8 lanes or more: P's last wp corners against Q's first wq, one
-//    pair per lane (wp * wq = L), each pair given mam5's test (bridge_pair).
+//  - With 8 lanes or more: first P's last wp corners against Q's first wq,
+//    one pair per lane (wp * wq = L), each pair given mam5's test
+//    (bridge_pair).  If none passes, tangent steps that alternate between
+//    the hoods: the L lanes classify Q's corners b .. b + L - 1 with g
+//    against P[a] and take the EQUAL one as the new b (the tangent corner of
+//    P[a], which lies at or right of b), then P's corners a .. a - L + 1
+//    with f against Q[b] for the new a, and so on from the junction pair
+//    (hp - 1, 0).  A step after the first that leaves its corner where it
+//    was ends the walk: then g(P[a], Q[b]) and f(Q[b], P[a]) are both
+//    EQUAL, mam5's test, which only the bridge passes.  A step that finds
+//    no EQUAL corner in its window, or PINGPONG_MAX steps without an end,
+//    leave it to the search.  (The window costs one step and catches the
+//    bridges within sqrt(L) corners of the junction; the tangent steps
+//    cover L corners on either side in two or three.)
 //  - With fewer: the group's first lane walks from the junction, at most
 //    WALK_MAX steps: Q's corner moves right while the next one is on or
 //    above the line P[a] -> Q[b] (g is LOW), P's moves left while the
@@ -316,6 +328,7 @@ __device__ __forceinline__ bool bridge_pair(PT P, int hp, PT Q, int hq, int i, i
 //    ends on the bridge; the end pair is checked with bridge_pair all the
 //    same, and a walk cut off by the step limit is not used.
 constexpr int WALK_MAX = 16;
+constexpr int PINGPONG_MAX = 8;
 
 template <class PT>
 __device__ __forceinline__ void bridge_find(PT P, int hp, PT Q, int hq, int L, int t, int base,
@@ -348,17 +361,40 @@ __device__ __forceinline__ void bridge_find(PT P, int hp, PT Q, int hq, int L, i
       return;
     }
   } else {
-    const int lg = 31 - __builtin_clz((unsigned)L);
-    const int lgq = lg >> 1;  // wq = 2^floor(lg / 2), wp = L / wq
-    const int i = hp - 1 - (t >> lgq), j = t & ((1 << lgq) - 1);
-    const bool hit = i >= 0 && j < hq && bridge_pair(P, hp, Q, hq, i, j, cnt, fe);
     const uint64_t gm = L == 64 ? ~0ull : ((1ull << L) - 1ull);
-    const uint64_t m = (__ballot(hit) >> base) & gm;
-    if (m) {
+    {  // the window: one pair per lane
+      const int lg = 31 - __builtin_clz((unsigned)L);
+      const int lgq = lg >> 1;  // wq = 2^floor(lg / 2), wp = L / wq
+      const int i = hp - 1 - (t >> lgq), j = t & ((1 << lgq) - 1);
+      const bool hit = i >= 0 && j < hq && bridge_pair(P, hp, Q, hq, i, j, cnt, fe);
+      const uint64_t m = (__ballot(hit) >> base) & gm;
+      if (m) {
+        const int k = __builtin_ctzll(m);
+        out_a = hp - 1 - (k >> lgq);
+        out_b = k & ((1 << lgq) - 1);
+        return;
+      }
+    }
+    int wa = hp - 1, wb = 0;  // tangent steps from the junction
+    for (int step = 0; step < PINGPONG_MAX; ++step) {
+      bool eq = false;
+      if ((step & 1) == 0) {  // Q's side: the tangent corner of P[wa]
+        const int j = wb + t;
+        eq = j < hq && g_classify(P[wa], Q, j, hq, cnt, fe) == EQUAL;
+      } else {                // P's side: the tangent corner of Q[wb]
+        const int i = wa - t;
+        eq = i >= 0 && f_classify(Q[wb], P, i, hp, cnt, fe) == EQUAL;
+      }
+      const uint64_t m = (__ballot(eq) >> base) & gm;
+      if (!m) break;  // not within L corners: the search decides
       const int k = __builtin_ctzll(m);
-      out_a = hp - 1 - (k >> lgq);
-      out_b = k & ((1 << lgq) - 1);
-      return;
+      if (k == 0 && step > 0) {  // no move: both classifiers EQUAL here
+        out_a = wa;
+        out_b = wb;
+        return;
+      }
+      if ((step & 1) == 0) wb += k;
+      else wa -= k;
     }
   }
   bridge_search<PT>(P, hp, Q, hq, L, t, base, out_a, out_b, cnt, fe);

@@ -291,6 +291,75 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// The hood of the entries of nleaf leaves blk[0 .. nleaf) (start, count) in
+// xy / id, in x order, at most 64 entries in all and every leaf non-empty,
+// by the direct corner test, run by one wave: lane e takes entry e and keeps
+// it iff it is a corner by the hood's definition -- no entry at its x is
+// higher, or as high with a lower index; and either no entry lies strictly
+// left (right) of it, or it lies strictly above the segment from its left
+// tangent point (of the entries strictly left of it, the one with the least
+// slope to it) to its right tangent point (of those strictly right, the one
+// with the greatest slope from it), the segment that lies highest at its x
+// among all that span it.  Every lane reads every entry from the lanes (the
+// same values in all), with one orientation test per entry: against the
+// left or the right tangent point, whichever side the entry is on.  The
+// corners go to xy / id from 0 on, in x order, and blk[0] = (0, count).
+// Depth: one pass of at most 64 tests, against log2(nleaf) rounds of merges.
+template <class ID>
+__device__ __forceinline__ void wave_direct_hood(float2 *xy, ID *id, int2 *blk, int nleaf,
+                                                 OrientCount &oc, bool fe) {
+  const int lane = threadIdx.x & 63;
+  const int2 lf = lane < nleaf ? blk[lane] : make_int2(0, 0);
+  int incl = lf.y;  // entries in leaves 0 .. lane
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const int vk = __builtin_amdgcn_readlane(incl, 63);
+  int li = 0;  // the leaf of entry `lane`
+  for (int k = 0; k < nleaf; ++k) li += __builtin_amdgcn_readlane(incl, k) <= lane ? 1 : 0;
+  li = min(li, 63);
+  const int excl = __shfl(incl - lf.y, li, 64), lo = __shfl(lf.x, li, 64);
+  float2 cp = make_float2(0.f, 0.f);
+  int ci = 0;
+  if (lane < vk) {
+    cp = xy[lo + lane - excl];
+    ci = (int)id[lo + lane - excl];
+  }
+  wave_sync();  // every entry is read before the corners overwrite them
+  bool hidden = lane >= vk, have_l = false, have_r = false;
+  float2 lt = cp, rt = cp;
+  for (int e = 0; e < vk; ++e) {
+    const float2 q = make_float2(readlane(cp.x, e), readlane(cp.y, e));
+    const int qi = __builtin_amdgcn_readlane(ci, e);
+    if (q.x == cp.x) {
+      hidden = hidden || q.y > cp.y || (q.y == cp.y && qi < ci);
+    } else {
+      const bool left = q.x < cp.x;
+      bool take = !(left ? have_l : have_r);
+      if (!take) {  // left: q beats lt if strictly left of lt -> c; right: c -> rt
+        const float2 u = left ? lt : cp, v = left ? cp : rt;
+        take = orient_sign(u, v, q, oc, fe) > 0;
+      }
+      if (take) {
+        if (left) lt = q;
+        else rt = q;
+      }
+      have_l = have_l || left;
+      have_r = have_r || !left;
+    }
+  }
+  const bool corner = !hidden && (!have_l || !have_r || orient_sign(lt, rt, cp, oc, fe) > 0);
+  const uint64_t cm = __ballot(corner);
+  if (corner) {
+    const int r = lanes_below(cm);
+    xy[r] = cp;
+    id[r] = (ID)ci;
+  }
+  if (lane == 0) blk[0] = make_int2(0, __builtin_popcountll(cm));
+  wave_sync();
+}
+
 // Adds a wave's orientation counters to stats[set].
 __device__ __forceinline__ void flush_wave_stats(const RunArgs &A, int set, OrientCount &oc) {
   if (!A.stats) return;
@@ -1042,6 +1111,11 @@ struct Rope {
   int k0, k1, c0;
   const float2 *lxy = nullptr;
   const int *lbase = nullptr;
+  // The first and the last child, where the searches next to the junction
+  // read: ranks below f_end are in child k0 at position f_pos + rank, ranks
+  // from l_beg on in child k1 - 1 at l_pos + rank (set by prep()).
+  int f_end = 0, l_beg = INT32_MAX;
+  int64_t f_pos = 0, l_pos = 0;
   // the child holding the item's element gi (cum[k0] <= gi < cum[k1])
   __device__ __forceinline__ int child(int gi) const {
     int l = k0, h = k1;
@@ -1052,18 +1126,21 @@ struct Rope {
     }
     return l;
   }
-  // workspace position of the item's element gi
-  __device__ __forceinline__ int64_t where(int gi) const {
-    const int l = child(gi);
-    return off + (int64_t)l * stride + lo[l] + (gi - cum[l]);
+  // position of child l's element of rank gi: in the workspace, or in the
+  // LDS copy
+  __device__ __forceinline__ int64_t pos(int l, int gi) const {
+    return (lxy ? (int64_t)lbase[l] : off + (int64_t)l * stride) + lo[l] + (gi - cum[l]);
+  }
+  __device__ __forceinline__ void prep() {
+    f_end = cum[k0 + 1];
+    f_pos = pos(k0, 0);
+    l_beg = cum[k1 - 1];
+    l_pos = pos(k1 - 1, 0);
   }
   __device__ __forceinline__ float2 operator[](int e) const {
     const int gi = c0 + e;
-    if (lxy) {
-      const int l = child(gi);
-      return lxy[lbase[l] + lo[l] + (gi - cum[l])];
-    }
-    return xy[where(gi)];
+    const int64_t p = gi < f_end ? f_pos + gi : gi >= l_beg ? l_pos + gi : pos(child(gi), gi);
+    return lxy ? lxy[p] : xy[p];
   }
 };
 
@@ -1403,63 +1480,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     }
     __syncthreads();
     if (direct) {
-      if (w == 0) {
-        // the kept entries of the leaves, flattened: lane e < vk holds entry
-        // e (found from the leaves' prefix counts)
-        const int nl = swave[NW];
-        const int2 lf = lane < nl ? sblk[lane] : make_int2(0, 0);
-        int incl = lf.y;
-        for (int d = 1; d < 64; d <<= 1) {
-          const int y = __shfl_up(incl, d, 64);
-          if (lane >= d) incl += y;
-        }
-        const int vk = __shfl(incl, 63, 64);
-        int li = 0;  // the leaf of entry `lane`
-        for (int k = 0; k < nl; ++k) li += __shfl(incl, k, 64) <= lane ? 1 : 0;
-        li = min(li, 63);
-        const int excl = __shfl(incl - lf.y, li, 64), lo = __shfl(lf.x, li, 64);
-        float2 ex = make_float2(0.f, 0.f);
-        int32_t ei = 0;
-        if (lane < vk) {
-          ex = bxy[lo + lane - excl];
-          ei = bid[lo + lane - excl];
-        }
-        wave_sync();  // every entry is read before the result overwrites them
-        // Lane c keeps entry c iff it is a corner of the hood of all vk
-        // entries, by the definition: no entry at its x is higher, or as
-        // high with a lower index; and either no entry lies strictly left
-        // (right) of it, or it lies strictly above the segment from its left
-        // tangent point (of the entries strictly left of it, the one with
-        // the least slope to it) to its right tangent point (of those
-        // strictly right, the one with the greatest slope from it), the
-        // segment that lies highest at its x among all that span it.  Every
-        // lane reads every entry from the lanes (the same values in all).
-        const float2 cp = ex;
-        bool hidden = lane >= vk, have_l = false, have_r = false;
-        float2 lt = cp, rt = cp;
-        for (int e = 0; e < vk; ++e) {
-          const float2 q = make_float2(readlane(ex.x, e), readlane(ex.y, e));
-          const int32_t qi = __builtin_amdgcn_readlane(ei, e);
-          if (q.x == cp.x) {
-            hidden = hidden || q.y > cp.y || (q.y == cp.y && qi < ei);
-          } else if (q.x < cp.x) {
-            if (!have_l || orient_sign(lt, cp, q, oc, fe) > 0) lt = q;
-            have_l = true;
-          } else {
-            if (!have_r || orient_sign(cp, rt, q, oc, fe) > 0) rt = q;
-            have_r = true;
-          }
-        }
-        const bool corner =
-            !hidden && (!have_l || !have_r || orient_sign(lt, rt, cp, oc, fe) > 0);
-        const uint64_t cm = __ballot(corner);
-        if (corner) {
-          const int r = lanes_below(cm);
-          bxy[r] = cp;
-          bid[r] = ei;
-        }
-        if (lane == 0) sblk[0] = make_int2(0, __builtin_popcountll(cm));
-      }
+      if (w == 0) wave_direct_hood(bxy, bid, sblk, swave[NW], oc, fe);
       __syncthreads();
     } else {
       if (nleaf_w > 0) {
@@ -1575,6 +1596,8 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         P.lxy = Q.lxy = lxy;
         P.lbase = Q.lbase = soff;
       }
+      P.prep();
+      Q.prep();
       int hp = cum[lq] - cum[lp], qs = 0;
       const int hq = cum[le] - cum[lq];
       if (hp > 0 && hq > 0) junction_rule(P[hp - 1], Q[0], hp, qs);
