@@ -83,31 +83,36 @@ __device__ __forceinline__ int orient_exact(float px, float py, float qx,
 // smallest non-zero product is 2^-60), so a zero bound means both products
 // are exactly zero and so is the determinant.  Contraction into FMA is off:
 // the bound assumes separately rounded products.
+// A lane that is not `live` (its result will be ignored; for branch-free
+// loops) gets the filter's sign, counts nothing and never takes the exact
+// path.
 __device__ __forceinline__ int orient_sign(float px, float py, float qx,
                                            float qy, float rx, float ry,
-                                           OrientCount &cnt, bool force_exact) {
+                                           OrientCount &cnt, bool force_exact,
+                                           bool live = true) {
 #pragma clang fp contract(off)
-  cnt.evals++;
+  cnt.evals += live ? 1u : 0u;
   const float dx1 = qx - px, dy1 = qy - py;
   const float dx2 = rx - px, dy2 = ry - py;
   const float l = dx1 * dy2;
   const float r = dy1 * dx2;
   const float det = l - r;
   const float bound = (__builtin_fabsf(l) + __builtin_fabsf(r)) * 0x1p-22f;
-  int sg;
-  if (!force_exact && (__builtin_fabsf(det) > bound || bound == 0.0f)) {
-    sg = (det > 0.0f) - (det < 0.0f);
-  } else {
+  int sg = (det > 0.0f) - (det < 0.0f);
+  // bitwise, so that the only branch is the one around the exact path
+  const bool decided =
+      !live | (!force_exact & ((__builtin_fabsf(det) > bound) | (bound == 0.0f)));
+  if (!decided) {
     cnt.fallbacks++;
     sg = orient_exact(px, py, qx, qy, rx, ry);
   }
-  if (cnt.check && sg != orient_int128(px, py, qx, qy, rx, ry)) cnt.sign_errors++;
+  if (cnt.check && live && sg != orient_int128(px, py, qx, qy, rx, ry)) cnt.sign_errors++;
   return sg;
 }
 
 __device__ __forceinline__ int orient_sign(float2 p, float2 q, float2 r,
-                                           OrientCount &cnt, bool fe) {
-  return orient_sign(p.x, p.y, q.x, q.y, r.x, r.y, cnt, fe);
+                                           OrientCount &cnt, bool fe, bool live = true) {
+  return orient_sign(p.x, p.y, q.x, q.y, r.x, r.y, cnt, fe, live);
 }
 
 // True only where the FP32 filter of orient_sign certifies that r lies

@@ -327,29 +327,31 @@ __device__ __forceinline__ void wave_direct_hood(float2 *xy, ID *id, int2 *blk, 
     ci = (int)id[lo + lane - excl];
   }
   wave_sync();  // every entry is read before the corners overwrite them
-  bool hidden = lane >= vk, have_l = false, have_r = false;
+  // Branch-free: every lane evaluates one test per entry, against the
+  // tangent point on the entry's side (a lane that needs no test evaluates
+  // it on its own point, an exact zero, and ignores it).
+  const bool valid = lane < vk;
+  bool hidden = !valid, have_l = false, have_r = false;
   float2 lt = cp, rt = cp;
   for (int e = 0; e < vk; ++e) {
     const float2 q = make_float2(readlane(cp.x, e), readlane(cp.y, e));
     const int qi = __builtin_amdgcn_readlane(ci, e);
-    if (q.x == cp.x) {
-      hidden = hidden || q.y > cp.y || (q.y == cp.y && qi < ci);
-    } else {
-      const bool left = q.x < cp.x;
-      bool take = !(left ? have_l : have_r);
-      if (!take) {  // left: q beats lt if strictly left of lt -> c; right: c -> rt
-        const float2 u = left ? lt : cp, v = left ? cp : rt;
-        take = orient_sign(u, v, q, oc, fe) > 0;
-      }
-      if (take) {
-        if (left) lt = q;
-        else rt = q;
-      }
-      have_l = have_l || left;
-      have_r = have_r || !left;
-    }
+    const bool same = q.x == cp.x, left = q.x < cp.x;
+    const bool have = left ? have_l : have_r;
+    // left: q replaces lt if strictly left of lt -> c; right: rt if
+    // strictly left of c -> rt
+    const float2 u = left ? lt : cp, v = left ? cp : rt;
+    const int sg = orient_sign(u, v, q, oc, fe, valid & !same & have);
+    const bool take = !same & (!have | (sg > 0));
+    hidden = hidden | (same & ((q.y > cp.y) | ((q.y == cp.y) & (qi < ci))));
+    lt = (take & left) ? q : lt;
+    rt = (take & !left) ? q : rt;
+    have_l = have_l | (!same & left);
+    have_r = have_r | (!same & !left);
   }
-  const bool corner = !hidden && (!have_l || !have_r || orient_sign(lt, rt, cp, oc, fe) > 0);
+  const bool spans = !hidden & have_l & have_r;
+  const int sc = orient_sign(lt, rt, cp, oc, fe, spans);
+  const bool corner = !hidden & (!spans | (sc > 0));
   const uint64_t cm = __ballot(corner);
   if (corner) {
     const int r = lanes_below(cm);
