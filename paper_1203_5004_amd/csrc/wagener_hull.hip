@@ -1100,6 +1100,16 @@ __device__ __forceinline__ int child_of(const int *soff, int n, int e) {
   return l;
 }
 
+// Four consecutive 32-bit or 8-byte elements moved as one access where the
+// four lie together (only 4-byte / 8-byte alignment is assumed: global
+// memory accepts such wide accesses unaligned).
+struct __attribute__((aligned(4))) Idx4 {
+  int32_t v[4];
+};
+struct __attribute__((aligned(8))) Xy4 {
+  float2 v[4];
+};
+
 // A block of the merge kernel's global path: children k0 .. k1 - 1, child k
 // keeping corners [lo[k], lo[k] + cum[k + 1] - cum[k]) of its slot; element
 // e of the block is element c0 + e of the item (cum: exclusive prefix of the
@@ -1548,30 +1558,56 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     // in registers and change when a position passes into the next child
     int kw = 0, kend = nch > 1 ? soff[1] : INT32_MAX, kcnt = bcnt[0];
     int64_t kbase = it.off;
-    for (int e0 = 0; e0 < V; e0 += 16 * BLK) {  // shared by all threads
-      float2 v8[16];
-      int dst[16];
+    auto child_at = [&](int e) {  // moves the cached child forward to e's
+      if (e >= kend) {
+        do ++kw;
+        while (kw + 1 < nch && soff[kw + 1] <= e);
+        kbase = it.off + (int64_t)kw * it.stride - soff[kw];
+        kend = kw + 1 < nch ? soff[kw + 1] : INT32_MAX;
+        kcnt = bcnt[kw] + soff[kw];
+      }
+    };
+    // four consecutive positions per thread step: one wide load where the
+    // four are kept corners of one child (positions past a child's kept
+    // corners are skipped), eight such steps in flight
+    for (int e0 = 0; e0 < V; e0 += 4 * 8 * BLK) {
+      Xy4 v8[8];
+      uint32_t wide = 0u, some = 0u;  // step u is one wide load / position 4u + q is kept
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = e0 + u * BLK + tid;
-        dst[u] = -1;
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 4 * (u * BLK + tid);
         if (e < V) {
-          if (e >= kend) {
-            do ++kw;
-            while (kw + 1 < nch && soff[kw + 1] <= e);
-            kbase = it.off + (int64_t)kw * it.stride - soff[kw];
-            kend = kw + 1 < nch ? soff[kw + 1] : INT32_MAX;
-            kcnt = bcnt[kw] + soff[kw];
-          }
-          if (e < kcnt) {
-            v8[u] = A.ws_xy[kbase + e];
-            dst[u] = e;
+          child_at(e);
+          if (e + 3 < kcnt) {  // kcnt <= kend: all four in this child, all kept
+            __builtin_memcpy(&v8[u], A.ws_xy + kbase + e, sizeof(Xy4));
+            wide |= 1u << u;
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              v8[u].v[q] = make_float2(0.f, 0.f);
+              if (e + q < V) {
+                child_at(e + q);
+                if (e + q < kcnt) {
+                  v8[u].v[q] = A.ws_xy[kbase + e + q];
+                  some |= 1u << (4 * u + q);
+                }
+              }
+            }
           }
         }
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (dst[u] >= 0) lxy[dst[u]] = v8[u];
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 4 * (u * BLK + tid);
+        if ((wide >> u) & 1u) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) lxy[e + q] = v8[u].v[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if ((some >> (4 * u + q)) & 1u) lxy[e + q] = v8[u].v[q];
+        }
+      }
     }
   }
   auto rescan = [&]() {
@@ -1647,17 +1683,34 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   };
   if (it.final_) {
     int32_t *dst = A.out_idx + set_base(A, it.set);
-    for (int e0 = 0; e0 < hc; e0 += 16 * BLK) {  // sixteen loads in flight
-      int32_t vi[16];
+    // four consecutive corners per thread step (one wide load where they
+    // lie in one child), eight steps in flight
+    for (int e0 = 0; e0 < hc; e0 += 4 * 8 * BLK) {
+      Idx4 vi[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = e0 + u * BLK + tid;
-        if (e < hc) vi[u] = A.ws_idx[where(e)];
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 4 * (u * BLK + tid);
+        if (e < hc) {
+          const int64_t p = where(e);
+          if (e + 3 < lend && e + 3 < hc) {
+            __builtin_memcpy(&vi[u], A.ws_idx + p, sizeof(Idx4));
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              vi[u].v[q] = e + q < hc ? A.ws_idx[where(e + q)] : 0;
+          }
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int e = e0 + u * BLK + tid;
-        if (e < hc) dst[e] = vi[u];
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + 4 * (u * BLK + tid);
+        if (e + 3 < hc) {
+          __builtin_memcpy(dst + e, &vi[u], sizeof(Idx4));
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (e + q < hc) dst[e + q] = vi[u].v[q];
+        }
       }
     }
     if (tid == 0) {
@@ -1669,29 +1722,52 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   } else {
     // compact to the item's slot: corner e comes from at or after slot
     // position e (a child keeps at most its slot's length), so a chunk read
-    // whole before it is written never overwrites a corner still to be read
-    for (int e0 = 0; e0 < hc; e0 += 8 * BLK) {
-      float2 vx[8];
-      int32_t vi[8];
+    // whole before it is written never overwrites a corner still to be read;
+    // the next chunk reads only at or after its own first position, past
+    // every position this one writes, so it needs no wait for these writes.
+    // Four consecutive corners per thread step, eight steps in flight.
+    for (int e0 = 0; e0 < hc; e0 += 4 * 8 * BLK) {
+      Xy4 vx[8];
+      Idx4 vi[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * BLK + tid;
+        const int e = e0 + 4 * (u * BLK + tid);
         if (e < hc) {
-          const int64_t src = where(e);
-          vx[u] = A.ws_xy[src];
-          vi[u] = A.ws_idx[src];
+          const int64_t p = where(e);
+          if (e + 3 < lend && e + 3 < hc) {
+            __builtin_memcpy(&vx[u], A.ws_xy + p, sizeof(Xy4));
+            __builtin_memcpy(&vi[u], A.ws_idx + p, sizeof(Idx4));
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              vx[u].v[q] = make_float2(0.f, 0.f);
+              vi[u].v[q] = 0;
+              if (e + q < hc) {
+                const int64_t pq = where(e + q);
+                vx[u].v[q] = A.ws_xy[pq];
+                vi[u].v[q] = A.ws_idx[pq];
+              }
+            }
+          }
         }
       }
-      __syncthreads();
+      __syncthreads();  // the chunk is read whole before any of it is written
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * BLK + tid;
-        if (e < hc) {
-          A.ws_xy[it.off + e] = vx[u];
-          A.ws_idx[it.off + e] = vi[u];
+        const int e = e0 + 4 * (u * BLK + tid);
+        if (e + 3 < hc) {
+          __builtin_memcpy(A.ws_xy + it.off + e, &vx[u], sizeof(Xy4));
+          __builtin_memcpy(A.ws_idx + it.off + e, &vi[u], sizeof(Idx4));
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (e + q < hc) {
+              A.ws_xy[it.off + e + q] = vx[u].v[q];
+              A.ws_idx[it.off + e + q] = vi[u].v[q];
+            }
+          }
         }
       }
-      __syncthreads();
     }
     if (tid == 0) cnt_out[blockIdx.x] = hc;
   }
