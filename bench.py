@@ -279,46 +279,55 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} steps, {plan.launches} launches per step)")
 
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    if args.flush:
-        # every step bracketed by its own events; the cache-clearing write between steps
-        # is outside them
-        scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    # Two timed passes of K steps each.  The step time comes from the first,
+    # with nothing but the library's own launches on the stream.  The tile
+    # kernel's duration comes from the second, with a pair of events recorded
+    # around the tile kernel of every step (the library's probe hook): an
+    # event recorded between two kernels holds the next launch back by some
+    # microseconds, so it stays out of the step time.
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev) if args.flush else None
+
+    def timed_pass(with_probes):
         marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                  for _ in range(args.steps)]
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        if scratch is None:
+            start.record()
         for k in range(args.steps):
-            scratch.fill_(float(k))
-            if probes:
-                plan.set_probe(*probes[k])
-            marks[k][0].record()
-            plan.run(pts, out_idx, out_cnt)
-            marks[k][1].record()
-        torch.cuda.synchronize()
-        total_ms = sum(a.elapsed_time(b) for a, b in marks)
-        del scratch
-    else:
-        torch.cuda.synchronize()
-        start.record()
-        for k in range(args.steps):
-            if probes:
+            if scratch is not None:
+                # cold caches: the cache-clearing write between steps is outside the
+                # step's own events
+                scratch.fill_(float(k))
+                marks[k][0].record()
+            if with_probes:
                 plan.set_probe(*probes[k])
             plan.run(pts, out_idx, out_cnt)
-        end.record()
+            if scratch is not None:
+                marks[k][1].record()
+        if scratch is None:
+            end.record()
         torch.cuda.synchronize()
-        total_ms = start.elapsed_time(end)
+        if with_probes:
+            plan.set_probe(None, None)
+        if scratch is not None:
+            return sum(a.elapsed_time(b) for a, b in marks)
+        return start.elapsed_time(end)
+
+    total_ms = timed_pass(False)
     ms_step = total_ms / args.steps
     value = N / (ms_step * 1e-3)
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {value:.4g} points/s")
 
     tile_ms = None
     if probes:
-        plan.set_probe(None, None)
+        timed_pass(True)
         tile_ms = sum(ev.elapsed_ms(a, b) for a, b in probes) / len(probes)
         for a, b in probes:
             ev.destroy(a)
             ev.destroy(b)
+    del scratch
 
     plain = None
     if args.compare_plain:
@@ -339,6 +348,8 @@ def main():
             plans[s].run(*views[s])
         torch.cuda.synchronize()
         reps = max(1, min(args.steps, 5))
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         start.record()
         for _ in range(reps):

@@ -293,22 +293,29 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 
 // The hood of the entries of nleaf leaves blk[0 .. nleaf) (start, count) in
 // xy / id, in x order, at most 64 entries in all and every leaf non-empty,
-// by the direct corner test, run by one wave: lane e takes entry e and keeps
-// it iff it is a corner by the hood's definition -- no entry at its x is
-// higher, or as high with a lower index; and either no entry lies strictly
-// left (right) of it, or it lies strictly above the segment from its left
-// tangent point (of the entries strictly left of it, the one with the least
-// slope to it) to its right tangent point (of those strictly right, the one
-// with the greatest slope from it), the segment that lies highest at its x
-// among all that span it.  Every lane reads every entry from the lanes (the
-// same values in all), with one orientation test per entry: against the
-// left or the right tangent point, whichever side the entry is on.  The
-// corners go to xy / id from 0 on, in x order, and blk[0] = (0, count).
-// Depth: one pass of at most 64 tests, against log2(nleaf) rounds of merges.
-template <class ID>
-__device__ __forceinline__ void wave_direct_hood(float2 *xy, ID *id, int2 *blk, int nleaf,
-                                                 OrientCount &oc, bool fe) {
-  const int lane = threadIdx.x & 63;
+// by the direct corner test: entry c is kept iff it is a corner by the
+// hood's definition -- no entry at its x is higher, or as high with a lower
+// index; and either no entry lies strictly left (right) of it, or it lies
+// strictly above the segment from its left tangent point (of the entries
+// strictly left of it, the one with the least slope to it) to its right
+// tangent point (of those strictly right, the one with the greatest slope
+// from it), the segment that lies highest at its x among all that span it.
+// Called by all NW waves of the workgroup.  Lane c of every wave takes entry
+// c; wave w scans the entries [w vk / NW, (w + 1) vk / NW) with one
+// orientation test each (against the tangent point on the entry's side),
+// then the waves' partial results are combined pairwise in log2(NW) rounds
+// through `part` / `pfl` (NW * 64 float4 and ints of LDS that overlap
+// neither xy[0 .. 64) nor id[0 .. 64)).  The tangent points are extremes of
+// slopes, so any grouping of the scan reaches the extreme; when several
+// collinear entries attain it, all lie on one ray from c and give the final
+// test the same sign.  Wave 0 writes the corners to xy / id from 0 on, in x
+// order, and blk[0] = (0, count).  Depth: vk / NW tests and log2(NW)
+// combining steps, against log2(nleaf) rounds of merges.
+template <int NW, class ID>
+__device__ __forceinline__ void block_direct_hood(float2 *xy, ID *id, int2 *blk, int nleaf,
+                                                  OrientCount &oc, bool fe, float4 *part,
+                                                  int *pfl) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int2 lf = lane < nleaf ? blk[lane] : make_int2(0, 0);
   int incl = lf.y;  // entries in leaves 0 .. lane
   for (int d = 1; d < 64; d <<= 1) {
@@ -326,14 +333,14 @@ __device__ __forceinline__ void wave_direct_hood(float2 *xy, ID *id, int2 *blk, 
     cp = xy[lo + lane - excl];
     ci = (int)id[lo + lane - excl];
   }
-  wave_sync();  // every entry is read before the corners overwrite them
+  __syncthreads();  // every entry is read before anything is written
   // Branch-free: every lane evaluates one test per entry, against the
   // tangent point on the entry's side (a lane that needs no test evaluates
   // it on its own point, an exact zero, and ignores it).
   const bool valid = lane < vk;
   bool hidden = !valid, have_l = false, have_r = false;
   float2 lt = cp, rt = cp;
-  for (int e = 0; e < vk; ++e) {
+  for (int e = w * vk / NW; e < (w + 1) * vk / NW; ++e) {
     const float2 q = make_float2(readlane(cp.x, e), readlane(cp.y, e));
     const int qi = __builtin_amdgcn_readlane(ci, e);
     const bool same = q.x == cp.x, left = q.x < cp.x;
@@ -349,17 +356,39 @@ __device__ __forceinline__ void wave_direct_hood(float2 *xy, ID *id, int2 *blk, 
     have_l = have_l | (!same & left);
     have_r = have_r | (!same & !left);
   }
-  const bool spans = !hidden & have_l & have_r;
-  const int sc = orient_sign(lt, rt, cp, oc, fe, spans);
-  const bool corner = !hidden & (!spans | (sc > 0));
-  const uint64_t cm = __ballot(corner);
-  if (corner) {
-    const int r = lanes_below(cm);
-    xy[r] = cp;
-    id[r] = (ID)ci;
+#pragma unroll
+  for (int st = 1; st < NW; st <<= 1) {  // wave w takes wave w + st's partial result
+    if ((w & (2 * st - 1)) == st) {
+      part[w * 64 + lane] = make_float4(lt.x, lt.y, rt.x, rt.y);
+      pfl[w * 64 + lane] = (hidden ? 1 : 0) | (have_l ? 2 : 0) | (have_r ? 4 : 0);
+    }
+    __syncthreads();
+    if ((w & (2 * st - 1)) == 0) {
+      const float4 o = part[(w + st) * 64 + lane];
+      const int f = pfl[(w + st) * 64 + lane];
+      const float2 ol = make_float2(o.x, o.y), orr = make_float2(o.z, o.w);
+      const bool ohl = (f & 2) != 0, ohr = (f & 4) != 0;
+      hidden = hidden | ((f & 1) != 0);
+      const int sl = orient_sign(lt, cp, ol, oc, fe, valid & have_l & ohl);
+      lt = (ohl & (!have_l | (sl > 0))) ? ol : lt;
+      have_l = have_l | ohl;
+      const int sr = orient_sign(cp, rt, orr, oc, fe, valid & have_r & ohr);
+      rt = (ohr & (!have_r | (sr > 0))) ? orr : rt;
+      have_r = have_r | ohr;
+    }
   }
-  if (lane == 0) blk[0] = make_int2(0, __builtin_popcountll(cm));
-  wave_sync();
+  if (w == 0) {
+    const bool spans = !hidden & have_l & have_r;
+    const int sc = orient_sign(lt, rt, cp, oc, fe, spans);
+    const bool corner = !hidden & (!spans | (sc > 0));
+    const uint64_t cm = __ballot(corner);
+    if (corner) {
+      const int r = lanes_below(cm);
+      xy[r] = cp;
+      id[r] = (ID)ci;
+    }
+    if (lane == 0) blk[0] = make_int2(0, __builtin_popcountll(cm));
+  }
 }
 
 // Adds a wave's orientation counters to stats[set].
@@ -1492,7 +1521,11 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     }
     __syncthreads();
     if (direct) {
-      if (w == 0) wave_direct_hood(bxy, bid, sblk, swave[NW], oc, fe);
+      // the partial results between the first 64 corner slots and the indices
+      static_assert(1024 + NW * 64 * 20 <= VMX * 8, "direct test scratch overlaps the indices");
+      block_direct_hood<NW>(bxy, bid, sblk, swave[NW], oc, fe,
+                            reinterpret_cast<float4 *>(lds_corners + 1024),
+                            reinterpret_cast<int *>(lds_corners + 1024 + NW * 64 * 16));
       __syncthreads();
     } else {
       if (nleaf_w > 0) {
