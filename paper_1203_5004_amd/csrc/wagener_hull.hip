@@ -250,6 +250,19 @@ __device__ __forceinline__ float row_suffix_max(float v, float id) {
   return v;
 }
 
+// Wave-level inclusive prefix sum of an integer (lanes at or below this
+// one), by DPP row shifts and row broadcasts: no trip through LDS.
+__device__ __forceinline__ int wave_prefix_sum(int v) {
+  const float z = __int_as_float(0);
+  v += __float_as_int(dpp<DPP_ROW_SHR + 1>(z, __int_as_float(v)));
+  v += __float_as_int(dpp<DPP_ROW_SHR + 2>(z, __int_as_float(v)));
+  v += __float_as_int(dpp<DPP_ROW_SHR + 4>(z, __int_as_float(v)));
+  v += __float_as_int(dpp<DPP_ROW_SHR + 8>(z, __int_as_float(v)));
+  v += __float_as_int(dpp<DPP_ROW_BCAST15, 0xa>(z, __int_as_float(v)));  // rows 1, 3 add rows 0, 2
+  v += __float_as_int(dpp<DPP_ROW_BCAST31, 0xc>(z, __int_as_float(v)));  // rows 2, 3 add rows 0-1
+  return v;
+}
+
 // Wave-level inclusive max scans (prefix: lanes below; suffix: lanes above).
 __device__ __forceinline__ float wave_prefix_max(float v, float id = -2.0f) {
   v = row_prefix_max(v, id);
@@ -317,11 +330,7 @@ __device__ __forceinline__ void block_direct_hood(float2 *xy, ID *id, int2 *blk,
                                                   int *pfl) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int2 lf = lane < nleaf ? blk[lane] : make_int2(0, 0);
-  int incl = lf.y;  // entries in leaves 0 .. lane
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += y;
-  }
+  const int incl = wave_prefix_sum(lf.y);  // entries in leaves 0 .. lane
   const int vk = __builtin_amdgcn_readlane(incl, 63);
   int li = 0;  // the leaf of entry `lane`
   for (int k = 0; k < nleaf; ++k) li += __builtin_amdgcn_readlane(incl, k) <= lane ? 1 : 0;
@@ -660,11 +669,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     // (with strips of 16 or 32 the height test's survivors were counted
     // already; only the chord tests can have left few)
     const int nk = __builtin_popcount(keep);
-    int koff = nk;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(koff, o, 64);
-      if (lane >= o) koff += y;
-    }
+    int koff = wave_prefix_sum(nk);
     const int nsurv = __shfl(koff, 63, 64);
     koff -= nk;
     if (!fin && nsurv <= TILE_LIST_MAX) {
@@ -696,11 +701,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     // strips, over survivors rather than over all points).  The chunk hoods
     // are the leaves: every chunk keeps at least one corner.
     const int nk = __builtin_popcount(keep);
-    int koff = nk;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(koff, o, 64);
-      if (lane >= o) koff += y;
-    }
+    int koff = wave_prefix_sum(nk);
     const int nsurv = __shfl(koff, 63, 64);
     koff -= nk;
     wave_sync();  // every lane is done with the strips in LDS
@@ -1041,11 +1042,7 @@ __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *ite
 template <int BLK>
 __device__ __forceinline__ int block_exclusive_scan(int v, int *swave, int &total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int x = v;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  const int x = wave_prefix_sum(v);
   if (lane == 63) swave[w] = x;
   __syncthreads();
   int before = 0;
@@ -1261,12 +1258,18 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     const int glo = it.level == 0 ? (int)blockIdx.x : it.child0;
     const int ghi = it.level == 0 ? (int)blockIdx.x : it.child0 + nch - 1;
     float gp = -2.0f, gs = -2.0f;
-    for (int k = tid; k < it.ng; k += BLK) {
-      const int gi = it.g0 + k;
-      if (gi < glo || gi > ghi) {
-        const float v = y_decode(A.group_max[gi * GROUP_STRIDE]);
-        if (gi < glo) gp = fmaxf(gp, v);
-        else gs = fmaxf(gs, v);
+    for (int k0 = 0; k0 < it.ng; k0 += 2 * BLK) {  // two loads in flight per thread
+      float v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = k0 + u * BLK + tid, gi = it.g0 + k;
+        v[u] = k < it.ng && (gi < glo || gi > ghi) ? y_decode(A.group_max[gi * GROUP_STRIDE]) : -2.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int gi = it.g0 + k0 + u * BLK + tid;
+        if (gi < glo) gp = fmaxf(gp, v[u]);
+        else gs = fmaxf(gs, v[u]);
       }
     }
     block_excl_max<BLK>(cm, gp, gs, wpre, wsuf, sw4);
