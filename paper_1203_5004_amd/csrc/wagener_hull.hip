@@ -1353,8 +1353,15 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     // in place; what is left of a strictly concave chain is still one, so
     // every child stays a hood.
     {
+      // A set's last merge with at most DIRECT_MAX entries gathered: the
+      // direct corner test below is exact on any points in x order (removing
+      // points that are no corners never changes the hood), so neither the
+      // elimination nor the chains of the point lists run first.  (An earlier
+      // merge filters all the same: its witnesses from the rest of the set
+      // drop points its own hood would keep and pass on.)
+      const bool few = !noelim && it.final_ && V <= DIRECT_MAX;
       float pre = wpre, suf = wsuf;
-      if (!known_max) {  // witnesses: the children's highest corners
+      if (!known_max && !few) {  // witnesses: the children's highest corners
         float cmax = -2.0f;
         for (int e0 = 0; e0 < c; e0 += 8) {  // eight LDS reads in flight
           float yv[8];
@@ -1366,7 +1373,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         block_excl_max<BLK>(cmax, -2.0f, -2.0f, pre, suf, sw4);
       }
       int kept = 0;
-      if (noelim) {
+      if (noelim || few) {
         kept = c;  // every gathered corner stays
       } else if (__syncthreads_or(c > 256)) {
         // Some child is large (an arc's steep end tiles, where nearly every
@@ -1490,7 +1497,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       }
       // a point-list child becomes a hood: the serial strip hood of its
       // surviving points (the paper's serial hoods of small strips)
-      if (pts && kept > 0) kept = chain_inplace(bxy + o, bid + o, kept, oc, fe);
+      if (pts && kept > 0 && !few) kept = chain_inplace(bxy + o, bid + o, kept, oc, fe);
       // leaves: the non-empty children, in order
       const uint64_t ne = __ballot(kept > 0);
       if (lane == 0) swave[w] = __builtin_popcountll(ne);
