@@ -571,12 +571,15 @@ __device__ __forceinline__ int chain_inplace(PT xy, IT id, int n, OrientCount &o
 }
 
 // Rounds of Wagener merges over nleaf <= 64 leaf hoods, run by one whole
-// wave: blk[0..nleaf) hold (base, count) of consecutive, x-adjacent,
-// non-empty hoods in the LDS arrays xy / id.  Round j joins blocks of 2^j
-// leaves; with M merges in a round each merge gets 64 / M lanes (the
-// paper's d1 x d2 block).  The hood of all leaves ends in blk[0].
+// wave: lane l holds leaf l's (base, count) in `blk` (l < nleaf), the leaves
+// being consecutive, x-adjacent, non-empty hoods in the LDS arrays xy / id.
+// Round j joins blocks of 2^j leaves; with M merges in a round each merge
+// gets 64 / M lanes (the paper's d1 x d2 block).  The leaf table stays in
+// registers: a merge reads its two blocks from their lanes and its result
+// goes back to the lane of its first block.  Returns the hood of all leaves
+// (base, count) in every lane.
 template <class ID>
-__device__ __forceinline__ void wave_rounds(float2 *xy, ID *id, int2 *blk, int nleaf,
+__device__ __forceinline__ int2 wave_rounds(float2 *xy, ID *id, int2 blk, int nleaf,
                                             OrientCount &oc, bool fe) {
   const int lane = threadIdx.x & 63;
   int lgn = 0;
@@ -585,17 +588,20 @@ __device__ __forceinline__ void wave_rounds(float2 *xy, ID *id, int2 *blk, int n
   for (int j = 0; j < lgn; ++j) {
     const int lgG = 6 - lgn + j + 1;
     const int t = lane & ((1 << lgG) - 1);
-    const int lp = (lane >> lgG) << (j + 1);
+    const int lp = (lane >> lgG) << (j + 1);  // < 2^lgn <= 64
     const int lq = lp + (1 << j);
-    if (lq < nleaf) {
-      const int2 P = blk[lp], Q = blk[lq];
-      int nb, nc;
-      merge_blocks(xy, id, P.x, P.y, Q.x, Q.y, lgG, t, lane - t, nb, nc, oc, fe);
-      wave_sync();
-      if (t == 0) blk[lp] = make_int2(nb, nc);
-    }
+    const int2 P = make_int2(__shfl(blk.x, lp, 64), __shfl(blk.y, lp, 64));
+    const int2 Q = make_int2(__shfl(blk.x, lq & 63, 64), __shfl(blk.y, lq & 63, 64));
+    int nb = P.x, nc = P.y;
+    if (lq < nleaf) merge_blocks(xy, id, P.x, P.y, Q.x, Q.y, lgG, t, lane - t, nb, nc, oc, fe);
     wave_sync();
+    // lane l, the first block of merge l >> (j + 1), takes that merge's
+    // result from the merge's first lane (unchanged where it had no partner)
+    const int src = ((lane >> (j + 1)) << lgG) & 63;
+    const int rb = __shfl(nb, src, 64), rc = __shfl(nc, src, 64);
+    if ((lane & ((2 << j) - 1)) == 0) blk = make_int2(rb, rc);
   }
+  return make_int2(__shfl(blk.x, 0, 64), __shfl(blk.y, 0, 64));
 }
 
 }  // namespace uh

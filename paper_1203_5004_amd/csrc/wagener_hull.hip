@@ -304,6 +304,21 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Position of set bit k (from 0, counting up from bit 0) of m, for
+// k < popcount(m): a binary search over the counts of m's lower bits.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {
+  int base = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const int c = __builtin_popcountll((m >> base) & ((1ull << w) - 1ull));
+    if (k >= c) {
+      k -= c;
+      base += w;
+    }
+  }
+  return base;
+}
+
 // The hood of the entries of nleaf leaves blk[0 .. nleaf) (start, count) in
 // xy / id, in x order, at most 64 entries in all and every leaf non-empty,
 // by the direct corner test: entry c is kept iff it is a corner by the
@@ -490,7 +505,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
                                           int32_t *cnt_out, const float2 (&p)[K],
                                           float nb_before, float nb_after, float2 set_first,
                                           float2 set_last, int err, bool fe,
-                                          float2 *sxy, uint16_t *sid, int2 *sblk) {
+                                          float2 *sxy, uint16_t *sid) {
   constexpr int S = K;
   const int lane = threadIdx.x;
   const bool fin = it.rel0 == 0 && it.len == it.set_len;  // the set's only tile
@@ -524,8 +539,6 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     if (ncand <= 4 * SPP) {
       // each segment of K lanes takes one candidate strip per pass; lane i of
       // the segment tests point i against the exact earlier / later maxima
-      reinterpret_cast<float2 *>(sblk)[lane] = make_float2(exp_pre, exp_suf);
-      wave_sync();
       const int seg = lane / K, i = lane % K;
       const int npass = (ncand + SPP - 1) / SPP;
       uint64_t rest = cand, kb[4];
@@ -548,7 +561,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
           for (int rr = 1; rr < SPP; ++rr) L = seg == rr ? Ls[rr] : L;
           const int Lc = L < 0 ? 0 : L;
           const float2 q = sxy[Lc * S + 2 * ((i >> 1) ^ tile_swz<K>(Lc)) + (i & 1)];
-          const float2 w = reinterpret_cast<const float2 *>(sblk)[Lc];
+          const float2 w = make_float2(__shfl(exp_pre, Lc, 64), __shfl(exp_suf, Lc, 64));
           float in_pre, in_post;
           segment_excl_max<K == 32 ? 32 : 16>(q.y, -2.0f, in_pre, in_post);
           const float before = fmaxf(w.x, in_pre);
@@ -575,7 +588,6 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
         if (err) atomicMin(&A.set_status[it.set], err);
         return;
       }
-      wave_sync();  // the hood path below reuses sblk
     }
   }
   uint32_t keep = 0;
@@ -691,6 +703,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
 
   // ---- 4. strip hoods, then rounds of Wagener merges over them
   int nleaf;
+  int2 leaf = make_int2(0, 0);  // lane l: leaf l (base, count)
   if (!noelim) {
     // After the eliminations most strips keep a point or two: serial hoods
     // of whole strips would leave up to 64 tiny leaves and six rounds of
@@ -722,8 +735,7 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     nleaf = (nsurv + C - 1) / C;
     if (lane < nleaf) {
       const int b = lane * C;
-      const int cnt = chain_inplace(sxy + b, sid + b, min(C, nsurv - b), oc, fe);
-      sblk[lane] = make_int2(b, cnt);
+      leaf = make_int2(b, chain_inplace(sxy + b, sid + b, min(C, nsurv - b), oc, fe));
     }
     wave_sync();
   } else {
@@ -757,13 +769,15 @@ __device__ __forceinline__ void tile_hood(const RunArgs &A, const TileItem &it, 
     // neighbouring leaves is merging hoods of x-adjacent point sets.
     const uint64_t ne = __ballot(cnt > 0);
     nleaf = __builtin_popcountll(ne);
-    if (cnt > 0) sblk[lanes_below(ne)] = make_int2(lane * S, cnt);
+    const int src = lane < nleaf ? nth_set_bit(ne, lane) : 0;  // the strip of leaf `lane`
+    const int csrc = __shfl(cnt, src, 64);
+    if (lane < nleaf) leaf = make_int2(src * S, csrc);
     wave_sync();
   }
-  wave_rounds(sxy, sid, sblk, nleaf, oc, fe);
+  leaf = wave_rounds(sxy, sid, leaf, nleaf, oc, fe);
 
   // ---- 5. output
-  const int hb = nleaf ? sblk[0].x : 0, hc = nleaf ? sblk[0].y : 0;
+  const int hb = nleaf ? leaf.x : 0, hc = nleaf ? leaf.y : 0;
   if (fin) {
     if (__ballot(err != 0)) err = wave_min(err);
     int32_t *dst = A.out_idx + (it.start - it.rel0);
@@ -865,7 +879,7 @@ __device__ __forceinline__ void tile_load(const RunArgs &A, const TileItem &it, 
 template <int K, bool BOTH>
 __device__ __forceinline__ void tile_process(const RunArgs &A, const TileItem &it, int tile,
                                              int32_t *cnt_out, const TileLoad<K> &L,
-                                             float2 *sxy, uint16_t *sid, int2 *sblk) {
+                                             float2 *sxy, uint16_t *sid) {
   constexpr int S = K;       // a strip's slot in LDS: K points, no padding
   constexpr int NV = K / 2;  // 16-byte slots (point pairs) per lane
   const int lane = threadIdx.x;
@@ -997,7 +1011,7 @@ __device__ __forceinline__ void tile_process(const RunArgs &A, const TileItem &i
     }
   }
   tile_hood<K>(A, it, tile, cnt_out, p, nb_before, nb_after, set_first, set_last, err, fe, sxy,
-               sid, sblk);
+               sid);
 
   if constexpr (BOTH) {
     // the lower hood: the same points mirrored in the x axis (the padding
@@ -1018,7 +1032,7 @@ __device__ __forceinline__ void tile_process(const RunArgs &A, const TileItem &i
     set_first.y = -set_first.y;
     set_last.y = -set_last.y;
     tile_hood<K>(A, lo, tile + A.lower_tiles, cnt_out, p, mb_before, mb_after, set_first,
-                 set_last, err, fe, sxy, sid, sblk);
+                 set_last, err, fe, sxy, sid);
   }
 }
 
@@ -1026,15 +1040,16 @@ __device__ __forceinline__ void tile_process(const RunArgs &A, const TileItem &i
 template <int K, bool BOTH>
 __global__ __launch_bounds__(64) void tile_kernel(RunArgs A, const TileItem *items,
                                                   int32_t *cnt_out, int32_t ntiles) {
+  // 10 KB at K = 16: sixteen waves per compute unit (the leaf table of the
+  // in-wave rounds lives in registers)
   __shared__ __attribute__((aligned(16))) float2 sxy[64 * K];
   __shared__ uint16_t sid[64 * K];
-  __shared__ int2 sblk[64];  // (base, count) of the block starting at each strip
 
   const int tile = blockIdx.x;
   const TileItem it = tile_item(A, items, tile, ntiles);
   TileLoad<K> ld;
   tile_load<K>(A, it, ld);
-  tile_process<K, BOTH>(A, it, tile, cnt_out, ld, sxy, sid, sblk);
+  tile_process<K, BOTH>(A, it, tile, cnt_out, ld, sxy, sid);
 }
 
 // ---------------------------------------------------------------- merges
@@ -1539,7 +1554,9 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       __syncthreads();
     } else {
       if (nleaf_w > 0) {
-        wave_rounds(bxy, bid, sblk + (w << 6), nleaf_w, oc, fe);
+        const int2 lf = lane < nleaf_w ? sblk[(w << 6) + lane] : make_int2(0, 0);
+        const int2 hood = wave_rounds(bxy, bid, lf, nleaf_w, oc, fe);
+        if (lane == 0) sblk[w << 6] = hood;
       } else if (lane == 0) {
         sblk[w << 6] = make_int2(0, 0);
       }
