@@ -1510,9 +1510,23 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
           }
         }
       }
-      // a point-list child becomes a hood: the serial strip hood of its
-      // surviving points (the paper's serial hoods of small strips)
-      if (pts && kept > 0 && !few) kept = chain_inplace(bxy + o, bid + o, kept, oc, fe);
+      // Few entries left: the workgroup finishes the merge by testing every
+      // entry against the hood's definition directly, whose depth beats that
+      // of log2(leaves) rounds of merges; the test takes any points, so the
+      // point lists need no hoods first.  Otherwise a point-list child
+      // becomes a hood (the serial strip hood of its surviving points, the
+      // paper's serial hoods of small strips), the leaves are dealt to the
+      // waves in contiguous runs of at most `per`, each wave runs the rounds
+      // over its run, and the wave hoods are joined pairwise in log2(waves)
+      // rounds.
+      int vk = kept;
+      for (int d = 1; d < 64; d <<= 1) vk += __shfl_xor(vk, d, 64);
+      if (lane == 0) sres[w] = make_int2(vk, 0);
+      __syncthreads();
+      int vsum = 0;
+      for (int k = 0; k < NW; ++k) vsum += sres[k].x;
+      direct = !noelim && vsum <= DIRECT_MAX;
+      if (pts && kept > 0 && !direct) kept = chain_inplace(bxy + o, bid + o, kept, oc, fe);
       // leaves: the non-empty children, in order
       const uint64_t ne = __ballot(kept > 0);
       if (lane == 0) swave[w] = __builtin_popcountll(ne);
@@ -1522,19 +1536,6 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         before += k < w ? swave[k] : 0;
         total += swave[k];
       }
-      // Few corners left: one wave finishes the merge by testing every
-      // corner against the hood's definition directly (a corner per lane),
-      // whose depth beats that of log2(leaves) rounds of merges.  Otherwise
-      // the leaves are dealt to the waves in
-      // contiguous runs of at most `per`, each wave runs the rounds over its
-      // run, and the wave hoods are joined pairwise in log2(waves) rounds.
-      int vk = kept;
-      for (int d = 1; d < 64; d <<= 1) vk += __shfl_xor(vk, d, 64);
-      if (lane == 0) sres[w] = make_int2(vk, 0);
-      __syncthreads();
-      int vsum = 0;
-      for (int k = 0; k < NW; ++k) vsum += sres[k].x;
-      direct = !noelim && vsum <= DIRECT_MAX;
       const int per = total > 0 ? (total + NW - 1) / NW : 1;
       if (kept > 0) {
         const int li = before + __builtin_popcountll(ne & ((1ull << lane) - 1ull));
