@@ -1393,7 +1393,9 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       } else if (__syncthreads_or(c > 256)) {
         // Some child is large (an arc's steep end tiles, where nearly every
         // point is a corner): the filter is shared by all threads, thread t
-        // taking entries [t * J, t * J + J) of the V gathered ones.  An entry
+        // taking entries [t * Jd, t * Jd + Jd) of the V gathered ones.  (A
+        // lower threshold, 64 or 128, sped up the first merge of arc_2^24's
+        // steep end but slowed the next pass's merges by more.)  An entry
         // needs the highest earlier entry of its own child (a segmented
         // prefix maximum over the threads) and, if kept, its rank among its
         // child's kept entries (a segmented prefix sum); then the kept
@@ -1408,15 +1410,16 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         }
         bcnt[tid] = 0;  // kept per child, filled below
         __syncthreads();
-        constexpr int J = (VMX + BLK - 1) / BLK;
-        const int e0 = tid * J;
+        constexpr int J = (VMX + BLK - 1) / BLK;  // at most J entries per thread
+        const int Jd = (V + BLK - 1) / BLK;        // this merge's: every thread takes a share
+        const int e0 = tid * Jd;
         const int k0 = e0 < V ? child_of<BLK>(soff, nch, e0) : 0;
         const bool starts = e0 < V && soff[k0] == e0;  // the chunk starts a child
         bool head = false;
         float m = -INFINITY;
         {
           int k = k0;
-          for (int j = 0; j < J && e0 + j < V; ++j) {
+          for (int j = 0; j < Jd && e0 + j < V; ++j) {
             const int e = e0 + j;
             while (k + 1 < nch && soff[k + 1] <= e) ++k;
             const float y = bxy[e].y;
@@ -1436,7 +1439,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         {
           int k = k0;
           float run = starts ? -INFINITY : mcarry;
-          for (int j = 0; j < J && e0 + j < V; ++j) {
+          for (int j = 0; j < Jd && e0 + j < V; ++j) {
             const int e = e0 + j;
             while (k + 1 < nch && soff[k + 1] <= e) ++k;
             if (soff[k] == e) {
@@ -1458,7 +1461,7 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         int32_t iv[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-          if (e0 + j < V) {
+          if (j < Jd && e0 + j < V) {
             qv[j] = bxy[e0 + j];
             iv[j] = bid[e0 + j];
           }
@@ -1470,15 +1473,17 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
 #pragma unroll
           for (int j = 0; j < J; ++j) {
             const int e = e0 + j;
-            if (e < V) {
+            if (j < Jd && e < V) {
               while (k + 1 < nch && soff[k + 1] <= e) ++k;
               if (soff[k] == e) r = 0;
               if ((keepbits >> j) & 1u) {
                 bxy[soff[k] + r] = qv[j];
                 bid[soff[k] + r] = iv[j];
                 ++r;
-                atomicMax(&bcnt[k], r);
               }
+              // the thread holding a child's last entry knows its count: one
+              // plain store per child, no atomic per kept entry
+              if (e + 1 == (k + 1 < nch ? soff[k + 1] : V)) bcnt[k] = r;
             }
           }
         }
