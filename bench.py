@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform_2^27")
     ap.add_argument("--strip", type=int, default=16)
+    ap.add_argument("--fan-in", type=int, default=0,
+                    help="merge fan-in of the plan (0: the library's default)")
     ap.add_argument("--graph", action="store_true", help="replay each step as a hipGraph")
     ap.add_argument("--force-fallback", action="store_true",
                     help="predicate ablation: every orientation test takes the exact FP64 path")
@@ -244,7 +246,7 @@ def main():
         (uh.UH_FLAG_NO_ELIMINATION if args.no_elimination else 0) | \
         (uh.UH_FLAG_CHECK_SIGNS if args.check_signs else 0)
     H = 2 if args.both_hoods else 1  # hoods per set
-    fan_in = 0
+    fan_in = args.fan_in
     tuned = None
     if args.autotune:
         t0 = time.perf_counter()

@@ -2007,27 +2007,19 @@ int cu_count() {
   return cus;
 }
 
-// Default fan-in: 256; for a plan of at least 8 tiles per compute unit (a
-// "large" plan), the largest of 256, 128, 64 that still gives the first merge
-// pass an item per compute unit.  A large set in few, large items would leave
-// most units idle while each item runs its rounds; a small plan keeps the
-// fewest passes.
+// Default fan-in: 256, the fewest merge passes, for every plan.  A "large"
+// plan (at least 8 tiles per compute unit) is flagged for the choice of the
+// wide merge workgroup.  (Halving the fan-in until the first merge pass has
+// an item per compute unit was slower, once the merges had become short:
+// arc_2^24 took 0.2593 ms per step at fan-in 64 and 0.2438 ms at 256,
+// uniform_2^27 0.2665 ms at 64, 0.2479 ms at 128 and 0.2289 ms at 256; the
+// mixed batch 1.97, 1.90 and 1.86 ms.  A pass fewer saves more than the
+// idle units of a first pass of few items cost.)
 int default_fan_in(const int64_t *off, int32_t S, int T, int cus, bool *large) {
   int64_t all_tiles = 0;
   for (int32_t s = 0; s < S; ++s) all_tiles += (off[s + 1] - off[s] + T - 1) / T;
   *large = all_tiles >= 8 * (int64_t)cus;
-  int F = BLOCK;
-  auto first_items = [&](int f) {
-    int64_t items = 0;
-    for (int32_t s = 0; s < S; ++s) {
-      const int64_t nt = (off[s + 1] - off[s] + T - 1) / T;
-      if (nt > 1) items += (nt + f - 1) / f;
-    }
-    return items;
-  };
-  if (*large)
-    while (F > 64 && first_items(F) < cus) F >>= 1;
-  return F;
+  return BLOCK;
 }
 
 // The passes of a single-set run, by the rules of upper_hull_plan_create.

@@ -415,22 +415,14 @@ def test_graph_replay_matches_eager():
     plan.close()
 
 
-def test_default_fan_in_fills_the_compute_units():
-    # one set of 2^24 points: 16384 tiles, 64 first-level items at fan-in 256
-    # would leave most units idle; the default takes 64 (256 items)
-    plan = uh.upper_hull_plan_create([0, 1 << 24])
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    F = plan.config["fan_in"]
-    assert F in (64, 128, 256)
-    assert -(-16384 // F) >= min(cus, 256) or F == 64
-    plan.close()
-    # many sets: the default stays 256; so does a small single set
-    plan = uh.upper_hull_plan_create(np.arange(0, 4097 * 5000, 5000))
-    assert plan.config["fan_in"] == 256
-    plan.close()
-    plan = uh.upper_hull_plan_create([0, 1 << 18])
-    assert plan.config["fan_in"] == 256
-    plan.close()
+def test_default_fan_in_takes_the_fewest_passes():
+    # the default fan-in is 256 for every plan shape: one large set (16384
+    # tiles: 64 first-level items), many sets, a small set; an explicit
+    # fan-in is kept
+    for off in ([0, 1 << 24], np.arange(0, 4097 * 5000, 5000), [0, 1 << 18]):
+        plan = uh.upper_hull_plan_create(off)
+        assert plan.config["fan_in"] == 256
+        plan.close()
     assert uh.upper_hull_plan_create([0, 100], fan_in=16).config["fan_in"] == 16
 
 
