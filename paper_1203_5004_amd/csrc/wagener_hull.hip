@@ -63,7 +63,8 @@ constexpr uint32_t POINTS_FLAG = 0x80000000u;
 constexpr int TILE_LIST_MAX = 64;  // most survivors a tile hands on as a list
 constexpr int DIRECT_MAX = 64;     // corners a merge finishes by the direct corner test
 // A group's maximum owns a 256-byte line of its own, so the atomics of the
-// tiles of different groups never queue behind one another.
+// tiles of different groups never queue behind one another.  (The second
+// word of a set's first group is the counter of a replicated last merge.)
 constexpr int GROUP_STRIDE = 64;
 
 struct TileItem {    // one tile of the tile pass (everything a tile needs: 32 bytes)
@@ -187,7 +188,10 @@ __device__ __forceinline__ void finish_stats(const RunArgs &A, int set, int32_t 
 // zero (a plan's own workspace can: every run's final merges zero them).
 __global__ void init_kernel(int32_t S, int32_t groups, RunArgs A) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < groups) A.group_max[(int64_t)s * GROUP_STRIDE] = 0u;
+  if (s < groups) {
+    A.group_max[(int64_t)s * GROUP_STRIDE] = 0u;
+    A.group_max[(int64_t)s * GROUP_STRIDE + 1] = 0u;  // the replicas' counter (merge_kernel)
+  }
   if (s >= S) return;
   A.set_status[s] = 0;
   if (A.stats) {
@@ -1223,10 +1227,14 @@ __device__ __forceinline__ MergeItem merge_item(const RunArgs &A, const MergeIte
 // children -> 1), then wave 0 merges the four wave hoods.  Otherwise the
 // same rounds run over the workspace (global memory), each merge by a group
 // of lanes, narrowing per-child intervals instead of moving corners.
+// reps > 1 (a last pass of few items): item i runs in workgroups i, i + items,
+// ..., i + (reps - 1) * items.  Over the workspace every replica finds the
+// same intervals (the rounds only read it) and gathers its own share of the
+// output; otherwise replica 0 does the merge and the others stop early.
 template <int BLK, int VMX>
 __global__ __launch_bounds__(BLK) void merge_kernel(
     RunArgs A, const MergeItem *items, PassArgs pa, const int32_t *child_cnt,
-    int32_t *cnt_out) {
+    int32_t *cnt_out, int32_t reps) {
   // VMX corners (x, y, index) for the LDS path; the global path reuses the
   // same bytes as 1.5 * VMX corner positions (x, y)
   __shared__ __attribute__((aligned(16))) char lds_corners[VMX * 12];
@@ -1240,7 +1248,11 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   __shared__ int swave[BLK / 64 + 1];
   __shared__ float4 sw4[BLK / 64];
 
-  const MergeItem it = merge_item(A, items, pa, (int)blockIdx.x);
+  const int nitems = (int)gridDim.x / reps;
+  const int rep = (int)blockIdx.x / nitems;        // replica of the item
+  const int item = (int)blockIdx.x - rep * nitems;
+  const MergeItem it = merge_item(A, items, pa, item);
+  if (rep > 0 && !it.final_) return;  // only a set's last merge is shared
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const bool fe = (A.flags & UH_FLAG_FORCE_FALLBACK) != 0;
@@ -1270,8 +1282,8 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
                      : it.level == 0 ? y_decode(A.tile_max[it.child0 + tid])
                                      : y_decode(A.group_max[(it.child0 + tid) * GROUP_STRIDE]);
     // the groups this item covers: its own (level 0) or its children (level 1)
-    const int glo = it.level == 0 ? (int)blockIdx.x : it.child0;
-    const int ghi = it.level == 0 ? (int)blockIdx.x : it.child0 + nch - 1;
+    const int glo = it.level == 0 ? item : it.child0;
+    const int ghi = it.level == 0 ? item : it.child0 + nch - 1;
     float gp = -2.0f, gs = -2.0f;
     for (int k0 = 0; k0 < it.ng; k0 += 2 * BLK) {  // two loads in flight per thread
       float v[2];
@@ -1311,7 +1323,30 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   int npow = 1;
   while (npow < nch) npow <<= 1;
   OrientCount oc = run_counter(A);
+  // the replicas share the merge over the workspace when no child is a
+  // point list (chaining those rewrites the workspace in place)
+  const bool shared = reps > 1 && V > VMX && !__syncthreads_or(pts);
   __syncthreads();
+  if (reps > 1) {
+    // The set's group maxima are zeroed for the next run once no replica
+    // will read them: with witnesses (first two levels), by the last replica
+    // to count itself in a counter kept in the second word of the set's
+    // first group maximum (which it sets back to zero); otherwise by replica 0.
+    __shared__ int s_last;
+    bool zero = rep == 0;
+    if (known_max) {
+      uint32_t *const ticket = A.group_max + (int64_t)it.g0 * GROUP_STRIDE + 1;
+      if (tid == 0) {
+        s_last = atomicAdd(ticket, 1u) == (uint32_t)(reps - 1);
+        if (s_last) atomicExch(ticket, 0u);
+      }
+      __syncthreads();
+      zero = s_last != 0;
+    }
+    if (zero)
+      for (int k = tid; k < it.ng; k += BLK) A.group_max[(it.g0 + k) * GROUP_STRIDE] = 0u;
+    if (rep > 0 && !shared) return;
+  }
 
   if (V <= VMX) {
     constexpr int NW = BLK / 64;  // waves
@@ -1594,10 +1629,10 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
           A.ws_xy[it.off + k] = bxy[hb + k];
           A.ws_idx[it.off + k] = bid[hb + k];
         }
-        if (lane == 0) cnt_out[blockIdx.x] = hc;
+        if (lane == 0) cnt_out[item] = hc;
       }
     }
-    if (it.final_)  // the set's group maxima, zero again for the next run
+    if (it.final_ && reps == 1)  // the set's group maxima, zero again for the next run
       for (int k = tid; k < it.ng; k += BLK) A.group_max[(it.g0 + k) * GROUP_STRIDE] = 0u;
     flush_wave_stats(A, it.set, oc);
     return;
@@ -1734,10 +1769,13 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
   // the result: corner e lives in child l with cum[l] <= e < cum[l + 1].  A
   // thread's positions only grow, so its child is found by walking forward
   // from the previous one (each child passed once) instead of a search.
+  // Replica r gathers corners [e_lo, e_hi) of a set's last merge.
   const int hc = cum[BLK];
-  int lw = 0;                                     // the child of the last position,
-  int64_t lbase = it.off + klo[0] - cum[0];       // its position minus its first rank,
-  int lend = nch > 1 ? cum[1] : INT32_MAX;        // and the rank where the next one starts
+  const int share = it.final_ ? (((hc + reps - 1) / reps + 3) & ~3) : hc;
+  const int e_lo = min(rep * share, hc), e_hi = min(e_lo + share, hc);
+  int lw = child_of<BLK>(cum, nch, e_lo);         // the child of the last position,
+  int64_t lbase = it.off + (int64_t)lw * it.stride + klo[lw] - cum[lw];  // its position minus its first rank,
+  int lend = lw + 1 < nch ? cum[lw + 1] : INT32_MAX;  // and the rank where the next one starts
   auto where = [&](int e) {
     if (e >= lend) {
       do ++lw;
@@ -1751,35 +1789,35 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
     int32_t *dst = A.out_idx + set_base(A, it.set);
     // four consecutive corners per thread step (one wide load where they
     // lie in one child), eight steps in flight
-    for (int e0 = 0; e0 < hc; e0 += 4 * 8 * BLK) {
+    for (int e0 = e_lo; e0 < e_hi; e0 += 4 * 8 * BLK) {
       Idx4 vi[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + 4 * (u * BLK + tid);
-        if (e < hc) {
+        if (e < e_hi) {
           const int64_t p = where(e);
-          if (e + 3 < lend && e + 3 < hc) {
+          if (e + 3 < lend && e + 3 < e_hi) {
             __builtin_memcpy(&vi[u], A.ws_idx + p, sizeof(Idx4));
           } else {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              vi[u].v[q] = e + q < hc ? A.ws_idx[where(e + q)] : 0;
+              vi[u].v[q] = e + q < e_hi ? A.ws_idx[where(e + q)] : 0;
           }
         }
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + 4 * (u * BLK + tid);
-        if (e + 3 < hc) {
+        if (e + 3 < e_hi) {
           __builtin_memcpy(dst + e, &vi[u], sizeof(Idx4));
         } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            if (e + q < hc) dst[e + q] = vi[u].v[q];
+            if (e + q < e_hi) dst[e + q] = vi[u].v[q];
         }
       }
     }
-    if (tid == 0) {
+    if (tid == 0 && rep == 0) {
       const int st = A.set_status[it.set];
       A.out_counts[it.set] = st ? st : hc;
       if (st) A.set_status[it.set] = 0;  // zero again for the next run
@@ -1835,11 +1873,11 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         }
       }
     }
-    if (tid == 0) cnt_out[blockIdx.x] = hc;
+    if (tid == 0) cnt_out[item] = hc;
   }
-  if (it.final_)  // the set's group maxima, zero again for the next run
+  if (it.final_ && reps == 1)  // the set's group maxima, zero again for the next run
     for (int k = tid; k < it.ng; k += BLK) A.group_max[(it.g0 + k) * GROUP_STRIDE] = 0u;
-  flush_wave_stats(A, it.set, oc);
+  if (rep == 0) flush_wave_stats(A, it.set, oc);
 }
 
 // ------------------------------------------------------------ convex hull
@@ -1989,6 +2027,7 @@ struct Launch {
   int32_t *cnt0 = nullptr;
   int npass = 0;
   int32_t pass_items[MAX_PASSES];
+  int32_t pass_reps[MAX_PASSES];  // workgroups per item (merge_kernel's reps)
   bool pass_wide[MAX_PASSES];
   const MergeItem *items[MAX_PASSES];
   int32_t *cnt[MAX_PASSES];
@@ -2020,6 +2059,15 @@ int default_fan_in(const int64_t *off, int32_t S, int T, int cus, bool *large) {
   for (int32_t s = 0; s < S; ++s) all_tiles += (off[s + 1] - off[s] + T - 1) / T;
   *large = all_tiles >= 8 * (int64_t)cus;
   return BLOCK;
+}
+
+// Workgroups per item of the last merge pass (all of its items are final
+// merges).  A last pass of few items runs each in several workgroups, which
+// share the gathering of a large hood: one workgroup gathers some 11 bytes
+// per cycle, about 23 us for the 45 800 corners of arc_2^24's hood.
+int32_t last_pass_reps(int32_t items, int cus) {
+  if (items <= 0 || items > 8) return 1;
+  return std::max(1, std::min(32, cus / (8 * items)));
 }
 
 // The passes of a single-set run, by the rules of upper_hull_plan_create.
@@ -2166,12 +2214,14 @@ int enqueue(const Launch &L, hipStream_t stream) {
   }
   for (int ps = 0; ps < L.npass; ++ps) {
     const int32_t *ccnt = ps == 0 ? L.cnt0 : L.cnt[ps - 1];
+    const int32_t reps = L.pass_reps[ps];
+    const dim3 grid((unsigned)(L.pass_items[ps] * reps));
     if (L.pass_wide[ps])
-      hipLaunchKernelGGL((merge_kernel<WIDE, VMAX_WIDE>), dim3(L.pass_items[ps]), dim3(WIDE), 0,
-                         stream, A, L.items[ps], L.pa[ps], ccnt, L.cnt[ps]);
+      hipLaunchKernelGGL((merge_kernel<WIDE, VMAX_WIDE>), grid, dim3(WIDE), 0, stream, A,
+                         L.items[ps], L.pa[ps], ccnt, L.cnt[ps], reps);
     else
-      hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), dim3(L.pass_items[ps]), dim3(BLOCK), 0,
-                         stream, A, L.items[ps], L.pa[ps], ccnt, L.cnt[ps]);
+      hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), grid, dim3(BLOCK), 0, stream, A,
+                         L.items[ps], L.pa[ps], ccnt, L.cnt[ps], reps);
   }
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
@@ -2198,6 +2248,7 @@ struct upper_hull_plan {
   int32_t *trace_cnt = nullptr;              // run counts of upper_hull_plan_trace
   uint32_t *tile_max = nullptr, *group_max = nullptr;
   std::vector<int32_t> pass_items;  // merge items per pass
+  int32_t last_reps = 1;            // workgroups per item of the last pass
   std::vector<char> pass_wide;      // per pass: the wide merge workgroup
   // device memory
   int64_t *d_set_start = nullptr;
@@ -2254,6 +2305,7 @@ Launch plan_launch(upper_hull_plan *p, const RunArgs &A, bool with_stats) {
   L.npass = (int)p->pass_items.size();
   for (int k = 0; k < L.npass; ++k) {
     L.pass_items[k] = p->pass_items[k];
+    L.pass_reps[k] = k + 1 == L.npass ? p->last_reps : 1;
     L.pass_wide[k] = p->pass_wide[k] != 0;
     L.items[k] = p->d_items.empty() ? nullptr : p->d_items[k];
     L.cnt[k] = p->d_cnt[k];
@@ -2337,7 +2389,8 @@ int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int3
   const int K = 16;
   bool large = false;
   const int64_t off[2] = {0, n};
-  const int F = default_fan_in(off, 1, 64 * K, cu_count(), &large);
+  const int cus = cu_count();
+  const int F = default_fan_in(off, 1, 64 * K, cus, &large);
   SingleShape sh;
   single_shape(n, both, K, F, large, sh);
   const bool bufs = hood_idx != nullptr;
@@ -2390,6 +2443,7 @@ int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int3
   La.npass = sh.npass;
   for (int k = 0; k < sh.npass; ++k) {
     La.pass_items[k] = sh.VS * sh.pass[k].items;
+    La.pass_reps[k] = k + 1 == sh.npass ? last_pass_reps(La.pass_items[k], cus) : 1;
     La.pass_wide[k] = sh.wide[k];
     La.items[k] = nullptr;
     La.cnt[k] = reinterpret_cast<int32_t *>(b + L.cnt[k]);
@@ -2670,6 +2724,7 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       p->pass_wide.push_back(wide);
     }
   }
+  if (!p->pass_items.empty()) p->last_reps = last_pass_reps(p->pass_items.back(), cu_count());
   p->h_voff = voff;
   p->h_tiles = tiles;
   p->h_items = passes;

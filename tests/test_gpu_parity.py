@@ -221,6 +221,39 @@ def test_determinism_repeated_runs():
         assert c1 == c0 and np.array_equal(i0, i1)
 
 
+def test_replicated_last_merge_repeated_runs():
+    # A last merge pass of few items runs each item in several workgroups
+    # that share the gathering of a large hood (here some 19 000 and 15 000
+    # corners, merged over the workspace).  The replicas count themselves in
+    # a word that must be back at zero for the next run, and the last of
+    # them clears the set's group maxima: every run of one plan must match.
+    a = synth.arc(1 << 20, 24, 4, seed=5)
+    b = synth.arc(1 << 19, 24, 4, seed=6)
+    u = synth.uniform(1 << 18, 24, seed=7)
+    for sets, flags in (([a], 0), ([a, b, u], 0), ([b], uh.UH_FLAG_BOTH_HOODS)):
+        pts, off = synth.concat_sets(sets)
+        S, N = len(sets), int(off[-1])
+        refs = [oracle.upper_hull_batched(pts, off)]
+        if flags:
+            refs.append(oracle.lower_hull_batched(pts, off))
+        H = len(refs)
+        plan = uh.upper_hull_plan_create(off, flags=flags)
+        d = _dev(pts)
+        for run in range(3):
+            out = torch.full((H * N,), -7, dtype=torch.int32, device="cuda")
+            cnt = torch.full((H * S,), -7, dtype=torch.int32, device="cuda")
+            plan.run(d, out, cnt, None)
+            torch.cuda.synchronize()
+            o, c = out.cpu().numpy(), cnt.cpu().numpy()
+            for h, (ref_out, ref_cnt) in enumerate(refs):
+                assert np.array_equal(c[h * S:(h + 1) * S], ref_cnt.astype(np.int32)), (flags, run, h)
+                for s in range(S):
+                    a0, k = int(off[s]), int(c[h * S + s])
+                    assert np.array_equal(o[h * N + a0:h * N + a0 + k], ref_out[a0:a0 + k]), \
+                        (flags, run, h, s)
+        plan.close()
+
+
 # ------------------------------------------------------------ data errors
 def test_data_errors_reported_per_set():
     good = synth.uniform(10000, 20, seed=3)
