@@ -1425,12 +1425,14 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
       int kept = 0;
       if (noelim || few) {
         kept = c;  // every gathered corner stays
-      } else if (__syncthreads_or(c > 256)) {
+      } else if (__syncthreads_or(c > 64)) {
         // Some child is large (an arc's steep end tiles, where nearly every
         // point is a corner): the filter is shared by all threads, thread t
-        // taking entries [t * Jd, t * Jd + Jd) of the V gathered ones.  (A
-        // lower threshold, 64 or 128, sped up the first merge of arc_2^24's
-        // steep end but slowed the next pass's merges by more.)  An entry
+        // taking entries [t * Jd, t * Jd + Jd) of the V gathered ones.  (Past
+        // 64 entries in one child the per-child loop below costs more:
+        // arc_2^24 took 0.223 ms per step with the shared filter past 256
+        // entries and 0.213 ms past 64, the mixed batch 1.860 and 1.842 ms;
+        // past 16 the parabola batch slowed by 1.5 %.)  An entry
         // needs the highest earlier entry of its own child (a segmented
         // prefix maximum over the threads) and, if kept, its rank among its
         // child's kept entries (a segmented prefix sum); then the kept
@@ -1449,16 +1451,29 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         const int Jd = (V + BLK - 1) / BLK;        // this merge's: every thread takes a share
         const int e0 = tid * Jd;
         const int k0 = e0 < V ? child_of<BLK>(soff, nch, e0) : 0;
-        const bool starts = e0 < V && soff[k0] == e0;  // the chunk starts a child
+        // Each walk over the thread's entries keeps its child's bounds and
+        // witnesses in registers and reads them from LDS only where it passes
+        // into the next child: the entries' own reads do not wait on a walk.
+        const int cs0 = soff[k0];                         // first entry of child k0
+        const int ce0 = k0 + 1 < nch ? soff[k0 + 1] : V;  // ... and past its last
+        const bool starts = e0 < V && cs0 == e0;  // the chunk starts a child
+        // child k holds [cs, ce): move on to the child holding e
+        auto step = [&](int e, int &k, int &cs, int &ce) {
+          while (e >= ce) {
+            ++k;
+            cs = ce;
+            ce = k + 1 < nch ? soff[k + 1] : V;
+          }
+        };
         bool head = false;
         float m = -INFINITY;
         {
-          int k = k0;
+          int k = k0, cs = cs0, ce = ce0;
           for (int j = 0; j < Jd && e0 + j < V; ++j) {
             const int e = e0 + j;
-            while (k + 1 < nch && soff[k + 1] <= e) ++k;
             const float y = bxy[e].y;
-            if (soff[k] == e) {
+            step(e, k, cs, ce);
+            if (cs == e) {
               head = true;
               m = y;
             } else {
@@ -1472,18 +1487,23 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         int nkept = 0;
         bool khead = false;
         {
-          int k = k0;
+          int k = k0, cs = cs0, ce = ce0;
+          float fp = fpre[k0], fs = fsuf[k0];
           float run = starts ? -INFINITY : mcarry;
           for (int j = 0; j < Jd && e0 + j < V; ++j) {
             const int e = e0 + j;
-            while (k + 1 < nch && soff[k + 1] <= e) ++k;
-            if (soff[k] == e) {
+            const float y = bxy[e].y;
+            if (e >= ce) {
+              step(e, k, cs, ce);
+              fp = fpre[k];
+              fs = fsuf[k];
+            }
+            if (cs == e) {
               run = -INFINITY;
               khead = true;
               nkept = 0;
             }
-            const float y = bxy[e].y;
-            if (y > fmaxf(fpre[k], run) || y >= fsuf[k]) {
+            if (y > fmaxf(fp, run) || y >= fs) {
               keepbits |= 1u << j;
               ++nkept;
             }
@@ -1503,22 +1523,22 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
         }
         __syncthreads();  // every entry is read before any moves
         {
-          int k = k0;
+          int k = k0, cs = cs0, ce = ce0;
           int r = starts ? 0 : rcarry;
 #pragma unroll
           for (int j = 0; j < J; ++j) {
             const int e = e0 + j;
             if (j < Jd && e < V) {
-              while (k + 1 < nch && soff[k + 1] <= e) ++k;
-              if (soff[k] == e) r = 0;
+              step(e, k, cs, ce);
+              if (cs == e) r = 0;
               if ((keepbits >> j) & 1u) {
-                bxy[soff[k] + r] = qv[j];
-                bid[soff[k] + r] = iv[j];
+                bxy[cs + r] = qv[j];
+                bid[cs + r] = iv[j];
                 ++r;
               }
               // the thread holding a child's last entry knows its count: one
               // plain store per child, no atomic per kept entry
-              if (e + 1 == (k + 1 < nch ? soff[k + 1] : V)) bcnt[k] = r;
+              if (e + 1 == ce) bcnt[k] = r;
             }
           }
         }
