@@ -203,8 +203,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the path shards by contiguous point ranges, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); "
+              "the path would shard by contiguous point ranges, one per GPU, their hoods "
+              "gathered to one GPU and merged there", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
