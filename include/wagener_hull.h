@@ -253,6 +253,9 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
  * (corners left to right, indices relative to set_offsets[s]) sits at
  * out_idx + set_offsets[num_sets] + set_offsets[s], its count at
  * out_counts[num_sets + s].  A data error is reported in both halves.
+ * A plan owns its run's working memory, including per-set words that every
+ * run leaves at zero for the next: runs of one plan must not overlap (keep
+ * them on one stream, or order them with events).
  */
 int upper_hull_plan_run(upper_hull_plan *plan, const float *points,
                         int32_t *out_idx, int32_t *out_counts,
