@@ -1227,14 +1227,16 @@ __device__ __forceinline__ MergeItem merge_item(const RunArgs &A, const MergeIte
 // children -> 1), then wave 0 merges the four wave hoods.  Otherwise the
 // same rounds run over the workspace (global memory), each merge by a group
 // of lanes, narrowing per-child intervals instead of moving corners.
-// reps > 1 (a last pass of few items): item i runs in workgroups i, i + items,
-// ..., i + (reps - 1) * items.  Over the workspace every replica finds the
+// order (or null: the identity) gives the item of each launch slot, the
+// largest items first.  reps > 1 (a last pass of few items): the item of slot
+// i runs in workgroups i, i + items, ..., i + (reps - 1) * items.  Over the
+// workspace every replica finds the
 // same intervals (the rounds only read it) and gathers its own share of the
 // output; otherwise replica 0 does the merge and the others stop early.
 template <int BLK, int VMX>
 __global__ __launch_bounds__(BLK) void merge_kernel(
-    RunArgs A, const MergeItem *items, PassArgs pa, const int32_t *child_cnt,
-    int32_t *cnt_out, int32_t reps) {
+    RunArgs A, const MergeItem *items, const int32_t *order, PassArgs pa,
+    const int32_t *child_cnt, int32_t *cnt_out, int32_t reps) {
   // VMX corners (x, y, index) for the LDS path; the global path reuses the
   // same bytes as 1.5 * VMX corner positions (x, y)
   __shared__ __attribute__((aligned(16))) char lds_corners[VMX * 12];
@@ -1250,7 +1252,8 @@ __global__ __launch_bounds__(BLK) void merge_kernel(
 
   const int nitems = (int)gridDim.x / reps;
   const int rep = (int)blockIdx.x / nitems;        // replica of the item
-  const int item = (int)blockIdx.x - rep * nitems;
+  const int slot = (int)blockIdx.x - rep * nitems;  // launch slot
+  const int item = order ? order[slot] : slot;
   const MergeItem it = merge_item(A, items, pa, item);
   if (rep > 0 && !it.final_) return;  // only a set's last merge is shared
   const int tid = threadIdx.x;
@@ -2050,6 +2053,7 @@ struct Launch {
   int32_t pass_reps[MAX_PASSES];  // workgroups per item (merge_kernel's reps)
   bool pass_wide[MAX_PASSES];
   const MergeItem *items[MAX_PASSES];
+  const int32_t *order[MAX_PASSES];  // launch slot -> item (null: identity)
   int32_t *cnt[MAX_PASSES];
   PassArgs pa[MAX_PASSES];
   bool init = false;         // launch init_kernel first
@@ -2238,10 +2242,10 @@ int enqueue(const Launch &L, hipStream_t stream) {
     const dim3 grid((unsigned)(L.pass_items[ps] * reps));
     if (L.pass_wide[ps])
       hipLaunchKernelGGL((merge_kernel<WIDE, VMAX_WIDE>), grid, dim3(WIDE), 0, stream, A,
-                         L.items[ps], L.pa[ps], ccnt, L.cnt[ps], reps);
+                         L.items[ps], L.order[ps], L.pa[ps], ccnt, L.cnt[ps], reps);
     else
       hipLaunchKernelGGL((merge_kernel<BLOCK, VMAX>), grid, dim3(BLOCK), 0, stream, A,
-                         L.items[ps], L.pa[ps], ccnt, L.cnt[ps], reps);
+                         L.items[ps], L.order[ps], L.pa[ps], ccnt, L.cnt[ps], reps);
   }
   return hipGetLastError() == hipSuccess ? UH_OK : UH_ERR_HIP;
 }
@@ -2275,6 +2279,7 @@ struct upper_hull_plan {
   TileItem *d_tiles = nullptr;
   int32_t *d_cnt0 = nullptr;
   std::vector<MergeItem *> d_items;
+  std::vector<int32_t *> d_order;  // per pass: launch slot -> item (null: identity)
   std::vector<int32_t *> d_cnt;   // per pass: item corner counts
   float2 *ws_xy = nullptr;
   int32_t *ws_idx = nullptr;
@@ -2299,6 +2304,7 @@ void free_plan_memory(upper_hull_plan *p) {
   (void)hipFree(p->d_tiles);
   (void)hipFree(p->d_cnt0);
   for (auto *q : p->d_items) (void)hipFree(q);
+  for (auto *q : p->d_order) (void)hipFree(q);
   for (auto *q : p->d_cnt) (void)hipFree(q);
   (void)hipFree(p->ws_xy);
   (void)hipFree(p->ws_idx);
@@ -2328,6 +2334,7 @@ Launch plan_launch(upper_hull_plan *p, const RunArgs &A, bool with_stats) {
     L.pass_reps[k] = k + 1 == L.npass ? p->last_reps : 1;
     L.pass_wide[k] = p->pass_wide[k] != 0;
     L.items[k] = p->d_items.empty() ? nullptr : p->d_items[k];
+    L.order[k] = p->d_order.empty() ? nullptr : p->d_order[k];
     L.cnt[k] = p->d_cnt[k];
     L.pa[k] = p->in_S == 1 ? p->single.pass[k] : PassArgs{};
   }
@@ -2466,6 +2473,7 @@ int run_single(const float *points, int64_t n, bool both, int32_t *out_idx, int3
     La.pass_reps[k] = k + 1 == sh.npass ? last_pass_reps(La.pass_items[k], cus) : 1;
     La.pass_wide[k] = sh.wide[k];
     La.items[k] = nullptr;
+    La.order[k] = nullptr;
     La.cnt[k] = reinterpret_cast<int32_t *>(b + L.cnt[k]);
     La.pa[k] = sh.pass[k];
   }
@@ -2764,6 +2772,21 @@ int upper_hull_plan_create(const int64_t *set_offsets, int32_t num_sets,
       rc = rc ? rc : dalloc(&di, passes[k].size());
       rc = rc ? rc : upload(di, passes[k]);
       p->d_items.push_back(di);
+      // launch order: the items with the most children first, so that the
+      // largest merges of a batch do not start last and leave a tail
+      std::vector<int32_t> ord(passes[k].size());
+      for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int32_t)i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        return passes[k][(size_t)a].nch > passes[k][(size_t)b].nch;
+      });
+      bool identity = true;
+      for (size_t i = 0; i < ord.size(); ++i) identity = identity && ord[i] == (int32_t)i;
+      int32_t *dord = nullptr;
+      if (!identity) {
+        rc = rc ? rc : dalloc(&dord, ord.size());
+        rc = rc ? rc : upload(dord, ord);
+      }
+      p->d_order.push_back(dord);
     }
     int32_t *dcnt = nullptr;
     rc = rc ? rc : dalloc(&dcnt, (size_t)p->pass_items[k]);
